@@ -1,0 +1,261 @@
+/*
+ * pie.h -- C ABI of the MI355X (gfx950) MLFMA library for the potential
+ * integral equations (PIEs) of perfectly conducting surfaces,
+ * after Gur & Ergul, "Solutions of New Potential Integral Equations Using
+ * MLFMA Based on the Approximate Stable Diagonalization" (arXiv:1806.04164).
+ *
+ * Problem (Section 2, Eqs. (1)-(2)): a closed triangulated surface S in free
+ * space at angular frequency w, exp(-i w t) convention; unknowns are the
+ * current J expanded in RWG functions (one per interior edge, E of them) and
+ * n.A expanded in pulse functions (one per triangle, T of them), N = E + T.
+ * Galerkin testing gives Z [a; b] = [b^J; b^A] with
+ *   Z^JJ = mu0 <f_m, int f_n g>, Z^JA = <div f_m, int P_p g>,
+ *   Z^AJ = <P_q, int div' f_n g>, Z^AA = w^2 eps0 <P_q, int P_p g>,
+ *   g = exp(i k R)/(4 pi R); b^J = -<f_m, A^inc>, b^A = -i w eps0 <P_q, Phi^inc>.
+ * The matrix-vector product is done with the MLFMA of Section 3: near-field
+ * entries for one-box-buffer neighbours, and aggregation, diagonal
+ * translation with the scaled plane waves of Eq. (4) and the modified
+ * translation function of Eq. (5), and disaggregation for the rest.
+ *
+ * Conventions for every call:
+ *  - Return value: PIE_OK (0), a negative error code, or a positive warning.
+ *    No exception crosses the ABI.  pie_last_error() returns the message of
+ *    the last failure on the calling thread.
+ *  - Handles are opaque, owned by the library, released by *_destroy.
+ *  - Arrays are owned by the caller.  "host" arrays are ordinary CPU memory;
+ *    "device" arrays are device pointers on the operator's GPU.
+ *  - Complex numbers are interleaved (re, im) doubles (complex128).
+ *  - Multi-RHS vectors are [N][R], R contiguous, unknowns in canonical order:
+ *    the E RWG coefficients in edge-table order, then the T pulse
+ *    coefficients in triangle order.
+ *  - Every argument is validated on the host before any device work, so
+ *    argument errors are reported without a GPU.
+ *  - An operator is used by one stream at a time; calls on the same operator
+ *    from different streams without ordering race.
+ */
+#ifndef PIE_H
+#define PIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pie_status;
+
+#define PIE_OK 0
+#define PIE_ERR_ARG (-1)         /* invalid argument (null, size, range)      */
+#define PIE_ERR_MESH (-2)        /* non-manifold, degenerate or misoriented   */
+#define PIE_ERR_NONFINITE (-3)   /* NaN or Inf in an input                    */
+#define PIE_ERR_PRECISION (-4)   /* translation table out of range for the    */
+                                 /* requested precision                      */
+#define PIE_ERR_OOM (-5)         /* device or host allocation failed          */
+#define PIE_ERR_HIP (-6)         /* HIP runtime error (message has details)   */
+#define PIE_ERR_UNSUPPORTED (-7) /* option combination not implemented        */
+#define PIE_WARN_NOT_CONVERGED 1 /* solver stopped at maxit above tolerance   */
+
+#define PIE_FP32 32
+#define PIE_FP64 64
+
+typedef struct pie_mesh pie_mesh;
+typedef struct pie_tree pie_tree;
+typedef struct pie_op pie_op;
+
+/* Copies the last error message of this thread into buf (NUL-terminated,
+ * truncated to len) and returns the full message length. */
+size_t pie_last_error(char* buf, size_t len);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t pie_version(void);
+
+/* ------------------------------------------------------------------ mesh --
+ * Section 2: RWG functions on the interior edges, pulses on the triangles.
+ * V: host double [nv][3] vertex coordinates (metres).
+ * T: host int32 [nt][3] vertex indices, counter-clockwise seen from outside.
+ * Edges are the vertex pairs (a < b) in ascending order; T+ is the triangle
+ * whose counter-clockwise cycle runs a->b.  Fails with PIE_ERR_MESH on a
+ * degenerate triangle, an edge shared by more than two triangles or
+ * inconsistent orientation; PIE_ERR_NONFINITE on NaN/Inf coordinates.
+ * Boundary edges (open surfaces) carry no RWG function. */
+pie_status pie_mesh_create(const double* V, int64_t nv, const int32_t* T,
+                           int64_t nt, pie_mesh** out);
+void pie_mesh_destroy(pie_mesh* m);
+/* nE: number of RWG functions, nT: number of triangles (pulses). */
+pie_status pie_mesh_sizes(const pie_mesh* m, int64_t* nE, int64_t* nT);
+/* Host int32 [nE][2] arrays (any may be NULL): edge vertices (a, b),
+ * triangles (T+, T-), free vertices (p+, p-). */
+pie_status pie_mesh_edges(const pie_mesh* m, int32_t* edges, int32_t* tri,
+                          int32_t* free_vertex);
+
+/* ------------------------------------------------------------------ tree --
+ * Section 3: the object is enclosed in a cubic box (vertex bounding box,
+ * side = its largest extent) divided recursively; level 1 is the root and
+ * levels >= 3 are required (3 = single-level FMM).  Basis reference points:
+ * RWG edge midpoint, pulse centroid.  Boxes of each level are the nonempty
+ * ones in Morton order (bit b of x,y,z -> bits 3b,3b+1,3b+2).  Unknowns are
+ * internally reordered by (finest box, RWG before pulse, canonical index).
+ * Near field: finest boxes within one box in every direction.  Far field at
+ * level l >= 3: same-level boxes not near but with near parents; offsets
+ * (obs - src) are numbered 0..315 over [-3,3]^3 with max|.| >= 2 in
+ * lexicographic (dx, dy, dz) order. */
+pie_status pie_tree_build(const pie_mesh* m, int32_t levels, pie_tree** out);
+void pie_tree_destroy(pie_tree* t);
+
+#define PIE_TQ_NBOX 1      /* level: count = boxes                            */
+#define PIE_TQ_COORDS 2    /* level: int64 [nb][3] integer box coordinates    */
+#define PIE_TQ_PARENT 3    /* level >= 2: int64 [nb] parent index             */
+#define PIE_TQ_PERM 4      /* int64 [N] canonical unknown at box-order slot   */
+#define PIE_TQ_BOXPTR 5    /* int64 [nb_L+1] box-order ranges of finest boxes */
+#define PIE_TQ_NEAR_PTR 6  /* int64 [nb_L+1] CSR of near boxes (incl. self)   */
+#define PIE_TQ_NEAR_IDX 7  /* int64 [nnz]                                     */
+#define PIE_TQ_IL_PTR 8    /* level >= 3: int64 [nb+1] interaction-list CSR   */
+#define PIE_TQ_IL_SRC 9    /* level >= 3: int64 [nnz] source boxes            */
+#define PIE_TQ_IL_OFF 10   /* level >= 3: int64 [nnz] offset ids 0..315       */
+/* Two-call query: with data == NULL only *count is set; otherwise data (host,
+ * int64, at least *count entries as returned by the first call) is filled. */
+pie_status pie_tree_query(const pie_tree* t, int32_t what, int32_t level,
+                          int64_t* count, int64_t* data);
+
+/* -------------------------------------------------------------- operator --
+ * MLFMA parameters (Eqs. (4)-(5)).  The paper tabulates the truncation
+ * number tau and scale factor s per box size in a reference that is not
+ * reproduced; here s_l = min(1, k d_l / x) per level, so that the scaled box
+ * size k d_l / s_l equals x wherever s < 1, and (tau, x) default per far
+ * precision to values chosen by measured error against the dense matrix:
+ *   far FP64: tau = 6, x = 0.07;  far FP32: tau = 4, x = 0.15.
+ * k-space samples: n_theta Gauss-Legendre points in cos(theta) (default
+ * tau+1) times n_phi uniform phi (default 2 tau + 2).
+ * near_prec: storage and arithmetic of the near-field SpMM.
+ * far_prec: patterns, translation and shifts.
+ * Tables (translation, filters) are always computed in FP64. */
+typedef struct pie_options {
+  int32_t version;   /* must be 1                                      */
+  int32_t near_prec; /* PIE_FP32 or PIE_FP64                           */
+  int32_t far_prec;  /* PIE_FP32 or PIE_FP64                           */
+  int32_t tau;       /* 0: default for far_prec                        */
+  double x;          /* 0: default for far_prec                        */
+  int32_t n_theta;   /* 0: tau + 1                                     */
+  int32_t n_phi;     /* 0: 2 tau + 2                                   */
+  int32_t max_rhs;   /* workspace is sized for up to this many RHS (>=1) */
+  int32_t reserved;  /* 0                                              */
+} pie_options;
+
+/* Fills *o with defaults (FP64 near and far, max_rhs 1). */
+void pie_options_default(pie_options* o);
+
+/* Builds the operator on the current HIP device: device geometry, near-field
+ * fill (FP64 arithmetic, closed-form singular parts for triangle pairs that
+ * share a vertex, symmetrised), translation tables and inter-level filters.
+ * mesh and tree must stay alive until the operator is destroyed.
+ * stream: hipStream_t (NULL = default stream); the call returns after the
+ * setup work on it has completed. */
+pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t,
+                               double freq_hz, const pie_options* opt,
+                               void* stream, pie_op** out);
+void pie_operator_destroy(pie_op* op);
+
+#define PIE_OI_N 1          /* number of unknowns                         */
+#define PIE_OI_Q 2          /* k-space samples per level                  */
+#define PIE_OI_TAU 3
+#define PIE_OI_NEAR_BLOCKS 4 /* stored (upper-triangle) near blocks       */
+#define PIE_OI_NEAR_ENTRIES 5 /* stored near-field entries                */
+#define PIE_OI_NEAR_BYTES 6  /* bytes of stored near-field entries        */
+#define PIE_OI_NBOX_FINEST 7
+#define PIE_OI_IL_PAIRS 8    /* interaction-list pairs over all levels    */
+#define PIE_OI_INCIDENCES 9  /* (finest box, triangle) incidences         */
+#define PIE_OI_DEVICE_BYTES 10 /* device memory held by the operator      */
+pie_status pie_operator_info(const pie_op* op, int32_t what, int64_t* value);
+/* Scale factor s and kappa = k/s at level l (3..L). */
+pie_status pie_operator_level(const pie_op* op, int32_t level, double* s,
+                              double* kappa, double* box_side);
+
+/* ------------------------------------------------------------------ MVM --
+ * y = Z x (adjoint = 0) or y = Z^H x (adjoint = 1) for R right-hand sides,
+ * 1 <= R <= max_rhs.  x, y: device complex128 [N][R], canonical order, must
+ * not overlap.  Asynchronous on stream (hipStream_t, NULL = default).
+ * Z^H x = conj(Z conj(x)) because the Galerkin matrix and its MLFMA
+ * approximation are complex symmetric (Z = Z^T); the adjoint path folds the
+ * two conjugations into its input and output kernels. */
+pie_status pie_matvec(pie_op* op, const void* x, void* y, int64_t R,
+                      int32_t adjoint, void* stream);
+
+/* Near-field part only (y = Z_near x) and far-field part only (y = Z_far x),
+ * same conventions as pie_matvec (used for per-stage parity and timing). */
+pie_status pie_matvec_near(pie_op* op, const void* x, void* y, int64_t R,
+                           void* stream);
+pie_status pie_matvec_far(pie_op* op, const void* x, void* y, int64_t R,
+                          void* stream);
+
+/* ------------------------------------------------------------ profile --
+ * Stage timing with HIP events recorded on the MVM stream around every
+ * kernel launch (each stage's events bracket exactly its kernels).
+ * pie_profile_enable(op, 1) clears the counters and starts recording;
+ * pie_profile_read waits for the recorded events and returns, per stage,
+ * the summed milliseconds (host double [PIE_NSTAGES]) and the number of
+ * launches (host int64 [PIE_NSTAGES]); either may be NULL. */
+#define PIE_STAGE_PERMUTE 0   /* canonical x -> box order (near precision) */
+#define PIE_STAGE_NEAR 1      /* near-field SpMM                           */
+#define PIE_STAGE_AGGREGATE 2 /* finest-level radiation patterns           */
+#define PIE_STAGE_SHIFT_UP 3  /* child -> parent shifts                    */
+#define PIE_STAGE_TRANSLATE 4 /* translation (+ parent -> child shift)     */
+#define PIE_STAGE_RECEIVE 5   /* reception + near join + output permutation */
+#define PIE_NSTAGES 6
+pie_status pie_profile_enable(pie_op* op, int32_t on);
+pie_status pie_profile_read(pie_op* op, double* ms, int64_t* launches);
+
+/* ---------------------------------------------------------------- RHS --
+ * Plane waves E^inc = amp_r pol_r exp(i k khat_r . r) (E0 = 1 V/m scale).
+ * khat, pol: host double [R][3] (unit, orthogonal); amp: host complex128 [R].
+ * gauge 0 (Lorenz, finite at zero frequency):
+ *   Phi = -amp (pol.r) e^{ik khat.r}, A = -(amp/c0)(pol.r) khat e^{ik khat.r};
+ * gauge 1: Phi = 0, A = E^inc/(i w).
+ * b: device complex128 [N][R]:  b^J_m = -<f_m, A^inc>,
+ * b^A_q = -i w eps0 <P_q, Phi^inc>, with the 7-point rule. */
+pie_status pie_rhs_planewave(pie_op* op, int64_t R, const double* khat,
+                             const double* pol, const double* amp,
+                             int32_t gauge, void* b, void* stream);
+
+/* -------------------------------------------------------------- solve --
+ * GMRES(restart) for Z x = b (Section 4) on the symmetrically equilibrated
+ * system D Z D (D = diag |Z_ii|^-1/2), FP64 orthogonalisation and residual.
+ * Each outer refinement step solves the correction equation with the
+ * operator's own precision and recomputes the residual b - Z x with the
+ * residual operator (if res_op is NULL, op itself).  x: device complex128
+ * [N][R] (input: initial guess if use_x0, output: solution).
+ * info (host, may be NULL) receives iterations and final relative residual
+ * per RHS. Returns PIE_WARN_NOT_CONVERGED if any RHS missed tol. */
+typedef struct pie_solve_opts {
+  int32_t version;    /* must be 1                                    */
+  int32_t restart;    /* Krylov dimension per cycle (default 100)     */
+  int32_t maxit;      /* total inner iterations per RHS (default 1000) */
+  int32_t refine;     /* outer refinement steps (default 1 = none)    */
+  double tol;         /* relative residual target (default 1e-6)      */
+  double inner_tol;   /* inner tolerance per refinement (default tol) */
+  int32_t use_x0;     /* 1: x holds the initial guess                 */
+  int32_t adjoint;    /* 1: solve Z^H x = b                           */
+} pie_solve_opts;
+typedef struct pie_solve_info {
+  int32_t iterations; /* total inner iterations (max over RHS)        */
+  int32_t refinements;
+  double rel_residual; /* max over RHS, with the residual operator     */
+} pie_solve_info;
+void pie_solve_opts_default(pie_solve_opts* o);
+pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void* x,
+                     int64_t R, const pie_solve_opts* opts,
+                     pie_solve_info* info, void* stream);
+
+/* ---------------------------------------------------------- far field --
+ * F(rhat) = lim r e^{-ikr} E^s = (i w mu0 / 4 pi)(I - rhat rhat).
+ *           int J(r') exp(-i k rhat.r') dr',  J = sum a_n f_n.
+ * x: device complex128 [N][R]; dirs: host double [nd][3] unit vectors;
+ * F: device complex128 [R][nd][3]. */
+pie_status pie_farfield(pie_op* op, const void* x, int64_t R,
+                        const double* dirs, int64_t nd, void* F,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIE_H */

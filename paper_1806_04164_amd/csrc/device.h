@@ -1,0 +1,127 @@
+// Device data descriptors and small helpers shared by the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pie {
+
+template <typename T>
+struct cx {
+  T re, im;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mk(T r, T i) {
+  return cx<T>{r, i};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(T s, cx<T> a) {
+  return {s * a.re, s * a.im};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) {
+  return {a.re, -a.im};
+}
+// a += b * c
+template <typename T>
+__device__ __forceinline__ void cfma(cx<T>& a, cx<T> b, cx<T> c) {
+  a.re = fma(b.re, c.re, a.re);
+  a.re = fma(-b.im, c.im, a.re);
+  a.im = fma(b.re, c.im, a.im);
+  a.im = fma(b.im, c.re, a.im);
+}
+// a += conj(b) * c
+template <typename T>
+__device__ __forceinline__ void cfma_conj(cx<T>& a, cx<T> b, cx<T> c) {
+  a.re = fma(b.re, c.re, a.re);
+  a.re = fma(b.im, c.im, a.re);
+  a.im = fma(b.re, c.im, a.im);
+  a.im = fma(-b.im, c.re, a.im);
+}
+template <typename T>
+__device__ __forceinline__ void sincos_t(T x, T* s, T* c);
+template <>
+__device__ __forceinline__ void sincos_t<float>(float x, float* s, float* c) {
+  sincosf(x, s, c);
+}
+template <>
+__device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c) {
+  sincos(x, s, c);
+}
+
+// Geometry (FP64).
+struct DevGeo {
+  const double* V;    // [nv][3]
+  const int32_t* T;   // [nt][3]
+  const double* P;    // [nt][7][3] quadrature points
+  const double* W;    // [nt][7] quadrature weights (area * rule weight)
+  const double* C;    // [nt][3] centroids
+  const double* Nrm;  // [nt][3] unit normals
+  int32_t nt;
+};
+
+// Basis functions in box order (slot u); canonical index perm[u];
+// RWG if perm[u] < ne.  Two halves per RWG (T+, T-): triangle, free vertex,
+// vector scale +-l/(2A) and divergence +-l/A.  Pulses use tri[2u] only.
+struct DevBasis {
+  const int32_t* perm;
+  const int32_t* tri;
+  const int32_t* fv;
+  const double* s;
+  const double* d;
+  int32_t N, ne;
+};
+
+// Stored near-field blocks (a <= b, Morton box indices), row-major n_a x n_b.
+struct DevNear {
+  int32_t nblk;
+  const int32_t* blk_a;
+  const int32_t* blk_b;
+  const int64_t* blk_off;   // entry offset of each block
+  const int32_t* prow;      // partial-sum slot of the block's rows
+  const int32_t* pcol;      // partial-sum slot of the block's columns (a < b)
+  const int32_t* box_ptr;   // [nbL+1] box-order unknown ranges
+  const int32_t* row_ptr;   // [nbL+1] blocks whose a is the box
+  const int32_t* col_ptr;   // [nbL+1] into col_blk
+  const int32_t* col_blk;   // blocks (a < b) whose b is the box
+};
+
+// One tree level.
+struct DevLevel {
+  int32_t nb;
+  const double* centre;     // [nb][3]
+  const int32_t* parent;    // [nb]
+  const int32_t* octant;    // [nb] position in the parent (bit0 x, bit1 y, bit2 z)
+  const int32_t* child_ptr; // [nb+1] into the next finer level
+  const int32_t* il_ptr;    // [nb+1]
+  const int32_t* il_src;
+  const int32_t* il_off;
+};
+
+// (finest box, triangle) incidences: up to three RWG functions of the box
+// that live on the triangle, and the triangle's pulse if it is in the box.
+struct DevInc {
+  const int32_t* ptr;   // [nbL+1]
+  const int32_t* tri;   // [ninc]
+  const int32_t* rwg;   // [ninc][3] box-order slot or -1
+  const double* rs;     // [ninc][3] +-l/(2A)
+  const double* rd;     // [ninc][3] +-l/A
+  const int32_t* rfv;   // [ninc][3] free vertex
+  const int32_t* pulse; // [ninc] box-order slot or -1
+  const int32_t* uslot; // [N][2] incidence*4 + k for each unknown (k = 3: pulse)
+};
+
+}  // namespace pie

@@ -1,0 +1,59 @@
+// Host-side launchers of the HIP kernels (each launcher returns the launch
+// error; kernels run asynchronously on the given stream).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace pie {
+
+// near.hip
+template <typename TN>
+hipError_t launch_near_fill(const DevGeo& G, const DevBasis& B, const DevNear& NB, void* out, double k,
+                            double w2e, hipStream_t st);
+hipError_t launch_diag(const DevGeo& G, const DevBasis& B, double* diag_abs, double k, double w2e,
+                       hipStream_t st);
+template <typename TN>
+hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part, int R,
+                            hipStream_t st);
+
+// far.hip
+size_t aggregate_smem(int maxpt, int RC, int tf_bytes);
+size_t receive_smem(int maxpt, int Q, int R, int RC, int tf_bytes);
+template <typename TF>
+hipError_t launch_aggregate(const DevGeo& G, const DevInc& I, const DevBasis& B, const double* boxC, int nb,
+                            int maxpt, const void* x, int ldx, int R, const void* khat, int Q, double kappa,
+                            double w2e, int conjx, void* S, hipStream_t st);
+template <typename TF>
+hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* Sc, void* Sp, const void* F,
+                           const void* ph, int Q, int ncol, hipStream_t st);
+template <typename TF>
+hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, void* Gout, int has_parent,
+                            const void* Gp, const void* Fp, const void* php, int Q, int ncol, hipStream_t st);
+template <typename TF, typename TN>
+hipError_t launch_receive(const DevGeo& G, const DevInc& I, const DevBasis& B, const DevNear& NB,
+                          const double* boxC, int nb, int maxpt, const void* Gin, const void* khat, int Q,
+                          double kappa, const void* part, int R, int flags, void* y, int ldy, hipStream_t st);
+template <typename TN>
+hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N, int R, int conjx, void* xb,
+                             hipStream_t st);
+
+// aux.hip
+hipError_t launch_rhs(const DevGeo& G, const double* basis_canon_s, const int32_t* tri_canon,
+                      const int32_t* fv_canon, int ne, int nt, const double* khat, const double* pol,
+                      const double* amp, int R, int gauge, double k, double omega, void* b, hipStream_t st);
+hipError_t launch_farfield(const DevGeo& G, const double* s_canon, const int32_t* tri_canon,
+                           const int32_t* fv_canon, int ne, const void* x, int R, const double* dirs, int nd,
+                           double k, double omega, void* F, hipStream_t st);
+// y[:, r] = alpha_r-free helpers for the solver (complex128, [N][R]).
+hipError_t launch_scale_rows(const void* x, const double* d, int N, int R, void* y, hipStream_t st);
+hipError_t launch_dots(const void* V, int64_t vstride, int nv, const void* w, int N, int R, void* out,
+                       hipStream_t st);
+hipError_t launch_update(void* w, const void* V, int64_t vstride, int nv, const void* h, int N, int R,
+                         hipStream_t st);
+hipError_t launch_norms(const void* w, int N, int R, double* out, hipStream_t st);
+hipError_t launch_colscale(void* w, const double* s, int N, int R, hipStream_t st);
+hipError_t launch_axpy_cols(void* x, const void* y, const void* a, int N, int R, hipStream_t st);
+hipError_t launch_sub(const void* a, const void* b, int N, int R, void* out, hipStream_t st);
+
+}  // namespace pie

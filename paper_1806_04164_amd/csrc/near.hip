@@ -1,0 +1,364 @@
+// Near-field interactions (Section 3: direct MoM entries of Eqs. (1)-(2) for
+// basis functions in one-box-buffer neighbour boxes): fill and SpMM.
+#include "device.h"
+#include "kernels.h"
+
+namespace pie {
+
+// ---------------------------------------------------------------------------
+// Fill: FP64 triangle-pair moments with the 7-point rule on both triangles;
+// for pairs that share a vertex, the static part 1/(4 pi R) of the inner
+// integral is done in closed form and the pair is averaged with its swap.
+// ---------------------------------------------------------------------------
+struct Mom {
+  cx<double> M0, Mo[3], Ms[3], Mos;
+};
+
+// int_T 1/|r-r'| and int_T (r' - rho)/|r-r'| over the triangle (a,b,c)
+// (rho = projection of r on its plane), summed edge by edge.
+__device__ void tri_potential(const double r[3], const double* va, const double* vb,
+                              const double* vc, const double nrm[3], double& K0, double K1[3]) {
+  const double d = nrm[0] * (r[0] - va[0]) + nrm[1] * (r[1] - va[1]) + nrm[2] * (r[2] - va[2]);
+  const double ad = fabs(d);
+  const double rho[3] = {r[0] - d * nrm[0], r[1] - d * nrm[1], r[2] - d * nrm[2]};
+  K0 = 0.0;
+  K1[0] = K1[1] = K1[2] = 0.0;
+  const double* vs[4] = {va, vb, vc, va};
+  for (int e = 0; e < 3; ++e) {
+    const double* a = vs[e];
+    const double* b = vs[e + 1];
+    double ed[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    double el = sqrt(ed[0] * ed[0] + ed[1] * ed[1] + ed[2] * ed[2]);
+    double lh[3] = {ed[0] / el, ed[1] / el, ed[2] / el};
+    // in-plane outward edge normal u = lhat x n
+    double uh[3] = {lh[1] * nrm[2] - lh[2] * nrm[1], lh[2] * nrm[0] - lh[0] * nrm[2],
+                    lh[0] * nrm[1] - lh[1] * nrm[0]};
+    double am[3] = {a[0] - rho[0], a[1] - rho[1], a[2] - rho[2]};
+    double bm[3] = {b[0] - rho[0], b[1] - rho[1], b[2] - rho[2]};
+    double t = am[0] * uh[0] + am[1] * uh[1] + am[2] * uh[2];
+    double sm = am[0] * lh[0] + am[1] * lh[1] + am[2] * lh[2];
+    double sp = bm[0] * lh[0] + bm[1] * lh[1] + bm[2] * lh[2];
+    double ra[3] = {r[0] - a[0], r[1] - a[1], r[2] - a[2]};
+    double rb[3] = {r[0] - b[0], r[1] - b[1], r[2] - b[2]};
+    double Rm = sqrt(ra[0] * ra[0] + ra[1] * ra[1] + ra[2] * ra[2]);
+    double Rp = sqrt(rb[0] * rb[0] + rb[1] * rb[1] + rb[2] * rb[2]);
+    double R0sq = t * t + d * d;
+    // R + s computed as R0^2/(R - s) when s < 0 (no cancellation)
+    double num = sp >= 0.0 ? Rp + sp : (Rp - sp > 0.0 ? R0sq / (Rp - sp) : 0.0);
+    double den = sm >= 0.0 ? Rm + sm : (Rm - sm > 0.0 ? R0sq / (Rm - sm) : 0.0);
+    double f = (num > 0.0 && den > 0.0) ? log(num / den) : 0.0;
+    double beta = atan2(t * sp, R0sq + ad * Rp) - atan2(t * sm, R0sq + ad * Rm);
+    K0 += t * f - ad * beta;
+    double g = 0.5 * (R0sq * f + sp * Rp - sm * Rm);
+    K1[0] += g * uh[0];
+    K1[1] += g * uh[1];
+    K1[2] += g * uh[2];
+  }
+}
+
+__device__ void raw_moments(const DevGeo& G, int ta, int tb, bool touch, double k, Mom& m) {
+  const double* Pa = G.P + 21 * ta;
+  const double* Pb = G.P + 21 * tb;
+  const double* Wa = G.W + 7 * ta;
+  const double* Wb = G.W + 7 * tb;
+  const double* ca = G.C + 3 * ta;
+  const double* cb = G.C + 3 * tb;
+  const double inv4pi = 0.25 / 3.14159265358979323846;
+  m.M0 = mk(0.0, 0.0);
+  m.Mos = mk(0.0, 0.0);
+  for (int d = 0; d < 3; ++d) m.Mo[d] = m.Ms[d] = mk(0.0, 0.0);
+  for (int i = 0; i < 7; ++i) {
+    double ra[3] = {Pa[3 * i] - ca[0], Pa[3 * i + 1] - ca[1], Pa[3 * i + 2] - ca[2]};
+    cx<double> gi = mk(0.0, 0.0);
+    cx<double> hi[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    for (int j = 0; j < 7; ++j) {
+      double dx = Pa[3 * i] - Pb[3 * j], dy = Pa[3 * i + 1] - Pb[3 * j + 1], dz = Pa[3 * i + 2] - Pb[3 * j + 2];
+      double R = sqrt(dx * dx + dy * dy + dz * dz);
+      cx<double> g;
+      if (!touch) {
+        double sn, cs;
+        sincos(k * R, &sn, &cs);
+        double f = inv4pi / R;
+        g = mk(cs * f, sn * f);
+      } else {
+        // (exp(ikR) - 1)/(4 pi R) = (ik/4pi) exp(ikR/2) sin(kR/2)/(kR/2)
+        double h = 0.5 * k * R;
+        double sinc = fabs(h) < 1e-4 ? 1.0 - h * h / 6.0 : sin(h) / h;
+        double sn, cs;
+        sincos(h, &sn, &cs);
+        double a = k * inv4pi * sinc;
+        g = mk(-a * sn, a * cs);
+      }
+      double ww = Wa[i] * Wb[j];
+      g = ww * g;
+      gi = gi + g;
+      double rb[3] = {Pb[3 * j] - cb[0], Pb[3 * j + 1] - cb[1], Pb[3 * j + 2] - cb[2]};
+      for (int d = 0; d < 3; ++d) hi[d] = hi[d] + rb[d] * g;
+    }
+    m.M0 = m.M0 + gi;
+    for (int d = 0; d < 3; ++d) {
+      m.Mo[d] = m.Mo[d] + ra[d] * gi;
+      m.Ms[d] = m.Ms[d] + hi[d];
+    }
+    m.Mos = m.Mos + (ra[0] * hi[0] + ra[1] * hi[1]) + ra[2] * hi[2];
+  }
+  if (touch) {
+    const double* va = G.V + 3 * G.T[3 * tb];
+    const double* vb = G.V + 3 * G.T[3 * tb + 1];
+    const double* vc = G.V + 3 * G.T[3 * tb + 2];
+    const double* nb = G.Nrm + 3 * tb;
+    for (int i = 0; i < 7; ++i) {
+      double r[3] = {Pa[3 * i], Pa[3 * i + 1], Pa[3 * i + 2]};
+      double K0, K1[3];
+      tri_potential(r, va, vb, vc, nb, K0, K1);
+      double dist = nb[0] * (r[0] - va[0]) + nb[1] * (r[1] - va[1]) + nb[2] * (r[2] - va[2]);
+      double K1c[3];
+      for (int d = 0; d < 3; ++d) K1c[d] = K1[d] + ((r[d] - dist * nb[d]) - cb[d]) * K0;
+      double w4 = Wa[i] * inv4pi;
+      double ra[3] = {r[0] - ca[0], r[1] - ca[1], r[2] - ca[2]};
+      m.M0.re += w4 * K0;
+      for (int d = 0; d < 3; ++d) {
+        m.Mo[d].re += w4 * K0 * ra[d];
+        m.Ms[d].re += w4 * K1c[d];
+      }
+      m.Mos.re += w4 * (ra[0] * K1c[0] + ra[1] * K1c[1] + ra[2] * K1c[2]);
+    }
+  }
+}
+
+__device__ bool touching(const DevGeo& G, int ta, int tb) {
+  const int32_t* A = G.T + 3 * ta;
+  const int32_t* B = G.T + 3 * tb;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (A[i] == B[j]) return true;
+  return false;
+}
+
+__device__ void pair_moments(const DevGeo& G, int ta, int tb, double k, Mom& m) {
+  bool t = touching(G, ta, tb);
+  raw_moments(G, ta, tb, t, k, m);
+  if (t) {
+    Mom s;
+    raw_moments(G, tb, ta, true, k, s);
+    m.M0 = 0.5 * (m.M0 + s.M0);
+    for (int d = 0; d < 3; ++d) {
+      cx<double> mo = 0.5 * (m.Mo[d] + s.Ms[d]);
+      cx<double> ms = 0.5 * (m.Ms[d] + s.Mo[d]);
+      m.Mo[d] = mo;
+      m.Ms[d] = ms;
+    }
+    m.Mos = 0.5 * (m.Mos + s.Mos);
+  }
+}
+
+// Z entry between box-order slots u (test) and v (source).
+__device__ cx<double> z_entry(const DevGeo& G, const DevBasis& B, int u, int v, double k, double w2e) {
+  const double mu0 = 4.0e-7 * 3.14159265358979323846;
+  const bool ur = B.perm[u] < B.ne;
+  const bool vr = B.perm[v] < B.ne;
+  cx<double> z = mk(0.0, 0.0);
+  Mom m;
+  if (ur && vr) {
+    for (int a = 0; a < 2; ++a) {
+      int ta = B.tri[2 * u + a];
+      const double* ca = G.C + 3 * ta;
+      const double* p = G.V + 3 * B.fv[2 * u + a];
+      double pa[3] = {p[0] - ca[0], p[1] - ca[1], p[2] - ca[2]};
+      for (int b = 0; b < 2; ++b) {
+        int tb = B.tri[2 * v + b];
+        const double* cb = G.C + 3 * tb;
+        const double* q = G.V + 3 * B.fv[2 * v + b];
+        double pb[3] = {q[0] - cb[0], q[1] - cb[1], q[2] - cb[2]};
+        pair_moments(G, ta, tb, k, m);
+        // (r-p).(r'-q) = (r-ca - pa).(r'-cb - pb)
+        cx<double> I1 = m.Mos;
+        I1 = I1 - ((pa[0] * m.Ms[0] + pa[1] * m.Ms[1]) + pa[2] * m.Ms[2]);
+        I1 = I1 - ((pb[0] * m.Mo[0] + pb[1] * m.Mo[1]) + pb[2] * m.Mo[2]);
+        I1 = I1 + (pa[0] * pb[0] + pa[1] * pb[1] + pa[2] * pb[2]) * m.M0;
+        z = z + (B.s[2 * u + a] * B.s[2 * v + b]) * I1;
+      }
+    }
+    z = mu0 * z;
+  } else if (ur && !vr) {
+    int tp = B.tri[2 * v];
+    for (int a = 0; a < 2; ++a) {
+      pair_moments(G, B.tri[2 * u + a], tp, k, m);
+      z = z + B.d[2 * u + a] * m.M0;
+    }
+  } else if (!ur && vr) {
+    int tq = B.tri[2 * u];
+    for (int b = 0; b < 2; ++b) {
+      pair_moments(G, tq, B.tri[2 * v + b], k, m);
+      z = z + B.d[2 * v + b] * m.M0;
+    }
+  } else {
+    pair_moments(G, B.tri[2 * u], B.tri[2 * v], k, m);
+    z = w2e * m.M0;
+  }
+  return z;
+}
+
+template <typename TN>
+__global__ void __launch_bounds__(256) k_near_fill(DevGeo G, DevBasis B, DevNear NB, cx<TN>* out,
+                                                   double k, double w2e, int32_t blk0) {
+  const int blk = blk0 + blockIdx.x;
+  const int a = NB.blk_a[blk], b = NB.blk_b[blk];
+  const int u0 = NB.box_ptr[a], na = NB.box_ptr[a + 1] - u0;
+  const int v0 = NB.box_ptr[b], nb = NB.box_ptr[b + 1] - v0;
+  cx<TN>* o = out + NB.blk_off[blk];
+  for (int e = threadIdx.x; e < na * nb; e += blockDim.x) {
+    int i = e / nb, j = e - i * nb;
+    cx<double> z = z_entry(G, B, u0 + i, v0 + j, k, w2e);
+    o[e] = mk((TN)z.re, (TN)z.im);
+  }
+}
+
+// Diagonal entries Z_uu (FP64) for the equilibration of the solver.
+__global__ void k_diag(DevGeo G, DevBasis B, double* diag_abs, double k, double w2e) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= B.N) return;
+  cx<double> z = z_entry(G, B, u, u, k, w2e);
+  diag_abs[u] = sqrt(z.re * z.re + z.im * z.im);
+}
+
+// ---------------------------------------------------------------------------
+// SpMM over the stored upper-triangle blocks.  One workgroup per block
+// (a, b): the row part r = Z_ab x_b goes to the partial slot of the rows, and
+// for a < b the transposed part c = Z_ab^T x_a (Z is symmetric) to the slot
+// of the columns.  Each wave owns rows i = wave, wave+4, ...; lanes run over
+// columns; row sums are wave reductions, column sums are lane-private and
+// combined across the four waves in a fixed order.  No atomics: the result
+// is bitwise reproducible.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename TN, int RC>
+__global__ void __launch_bounds__(256) k_near_spmm(DevNear NB, const cx<TN>* __restrict__ Z,
+                                                   const cx<TN>* __restrict__ xb, int ldx,
+                                                   cx<TN>* __restrict__ part, int R) {
+  constexpr int MAXB = 128;  // max unknowns per box handled (checked on the host)
+  __shared__ cx<TN> xa_s[MAXB * RC];
+  __shared__ cx<TN> xbb_s[MAXB * RC];
+  __shared__ cx<TN> col_s[4][MAXB * RC];
+  const int blk = blockIdx.x;
+  const int a = NB.blk_a[blk], b = NB.blk_b[blk];
+  const int u0 = NB.box_ptr[a], na = NB.box_ptr[a + 1] - u0;
+  const int v0 = NB.box_ptr[b], nb = NB.box_ptr[b + 1] - v0;
+  const bool offdiag = a != b;
+  for (int e = threadIdx.x; e < nb * R; e += blockDim.x) {
+    int j = e / R, r = e - j * R;
+    xbb_s[j * RC + r] = xb[(size_t)(v0 + j) * ldx + r];
+  }
+  if (offdiag)
+    for (int e = threadIdx.x; e < na * R; e += blockDim.x) {
+      int i = e / R, r = e - i * R;
+      xa_s[i * RC + r] = xb[(size_t)(u0 + i) * ldx + r];
+    }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const cx<TN>* Zb = Z + NB.blk_off[blk];
+  cx<TN> cacc[2][RC];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < RC; ++r) cacc[h][r] = mk<TN>(0, 0);
+  cx<TN>* prow = part + (size_t)NB.prow[blk] * R;
+  for (int i = wave; i < na; i += 4) {
+    cx<TN> racc[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) racc[r] = mk<TN>(0, 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      int j = lane + 64 * h;
+      if (j < nb) {
+        cx<TN> z = Zb[(size_t)i * nb + j];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+          if (r < R) {
+            cfma(racc[r], z, xbb_s[j * RC + r]);
+            if (offdiag) cfma(cacc[h][r], z, xa_s[i * RC + r]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      if (r < R) {
+        TN re = wave_sum(racc[r].re), im = wave_sum(racc[r].im);
+        if (lane == 0) prow[(size_t)i * R + r] = mk(re, im);
+      }
+    }
+  }
+  if (offdiag) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      int j = lane + 64 * h;
+      if (j < nb)
+#pragma unroll
+        for (int r = 0; r < RC; ++r)
+          if (r < R) col_s[wave][j * RC + r] = cacc[h][r];
+    }
+    __syncthreads();
+    cx<TN>* pcol = part + (size_t)NB.pcol[blk] * R;
+    for (int e = threadIdx.x; e < nb * R; e += blockDim.x) {
+      int j = e / R, r = e - j * R;
+      cx<TN> s = col_s[0][j * RC + r];
+      s = s + col_s[1][j * RC + r];
+      s = s + col_s[2][j * RC + r];
+      s = s + col_s[3][j * RC + r];
+      pcol[(size_t)j * R + r] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers --
+template <typename TN>
+hipError_t launch_near_fill(const DevGeo& G, const DevBasis& B, const DevNear& NB, void* out,
+                            double k, double w2e, hipStream_t st) {
+  const int chunk = 4096;
+  for (int b0 = 0; b0 < NB.nblk; b0 += chunk) {
+    int n = NB.nblk - b0 < chunk ? NB.nblk - b0 : chunk;
+    hipLaunchKernelGGL(k_near_fill<TN>, dim3(n), dim3(256), 0, st, G, B, NB, (cx<TN>*)out, k, w2e, b0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+template hipError_t launch_near_fill<float>(const DevGeo&, const DevBasis&, const DevNear&, void*,
+                                            double, double, hipStream_t);
+template hipError_t launch_near_fill<double>(const DevGeo&, const DevBasis&, const DevNear&, void*,
+                                             double, double, hipStream_t);
+
+hipError_t launch_diag(const DevGeo& G, const DevBasis& B, double* diag_abs, double k, double w2e,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_diag, dim3((B.N + 127) / 128), dim3(128), 0, st, G, B, diag_abs, k, w2e);
+  return hipGetLastError();
+}
+
+template <typename TN>
+hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part,
+                            int R, hipStream_t st) {
+  if (NB.nblk == 0) return hipSuccess;
+  if (R <= 1)
+    hipLaunchKernelGGL((k_near_spmm<TN, 1>), dim3(NB.nblk), dim3(256), 0, st, NB, (const cx<TN>*)Z,
+                       (const cx<TN>*)xb, ldx, (cx<TN>*)part, R);
+  else if (R <= 2)
+    hipLaunchKernelGGL((k_near_spmm<TN, 2>), dim3(NB.nblk), dim3(256), 0, st, NB, (const cx<TN>*)Z,
+                       (const cx<TN>*)xb, ldx, (cx<TN>*)part, R);
+  else
+    hipLaunchKernelGGL((k_near_spmm<TN, 4>), dim3(NB.nblk), dim3(256), 0, st, NB, (const cx<TN>*)Z,
+                       (const cx<TN>*)xb, ldx, (cx<TN>*)part, R);
+  return hipGetLastError();
+}
+template hipError_t launch_near_spmm<float>(const DevNear&, const void*, const void*, int, void*, int,
+                                            hipStream_t);
+template hipError_t launch_near_spmm<double>(const DevNear&, const void*, const void*, int, void*, int,
+                                             hipStream_t);
+
+}  // namespace pie

@@ -1,0 +1,1208 @@
+// Operator setup, MVM orchestration, GMRES and the C ABI.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "pie_internal.h"
+
+using pie::cx;
+
+namespace pie {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace pie
+
+struct pie_mesh {
+  pie::Mesh m;
+};
+struct pie_tree {
+  pie::Tree t;
+};
+
+struct pie_op {
+  const pie::Mesh* mesh = nullptr;
+  const pie::Tree* tree = nullptr;
+  int device = 0;
+  double freq = 0, omega = 0, k = 0, w2e = 0;
+  int near_prec = 64, far_prec = 64, tau = 0, nth = 0, nph = 0, Q = 0;
+  double xs = 0;
+  int max_rhs = 1, rc = 1, L = 0, N = 0, ne = 0, nt = 0;
+  int maxpt = 0;
+  // device geometry
+  double *dV = nullptr, *dP = nullptr, *dW = nullptr, *dC = nullptr, *dN = nullptr;
+  int32_t* dT = nullptr;
+  // basis in box order and in canonical order
+  int32_t *dPerm = nullptr, *dBtri = nullptr, *dBfv = nullptr;
+  double *dBs = nullptr, *dBd = nullptr;
+  int32_t *dCtri = nullptr, *dCfv = nullptr;
+  double* dCs = nullptr;
+  // near field
+  pie::DevNear NB{};
+  void* dNear = nullptr;
+  int64_t near_entries = 0, nslots = 0;
+  // incidences
+  pie::DevInc I{};
+  int64_t ninc = 0;
+  // levels (index l)
+  std::vector<pie::DevLevel> lv;
+  std::vector<double> s_l, kappa_l, d_l;
+  int64_t il_pairs = 0;
+  // tables in far precision
+  void* dKhat = nullptr;
+  std::vector<void*> dTl, dFl, dPhl;
+  // workspace
+  std::vector<void*> dS, dG;
+  void* dPart = nullptr;
+  void* dXb = nullptr;
+  double* dDiagScale = nullptr;  // |Z_uu|^-1/2, canonical order
+  double *dKhR = nullptr, *dPolR = nullptr, *dAmpR = nullptr, *dDirs = nullptr;
+  int64_t ndirs_cap = 0;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  // stage profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+  ~pie_op() {
+    for (auto& u : ev_used) {
+      (void)hipEventDestroy(u.second.first);
+      (void)hipEventDestroy(u.second.second);
+    }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+using namespace pie;
+
+pie_status hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? PIE_ERR_OOM : PIE_ERR_HIP;
+}
+
+#define HIPCHK(expr, what)                    \
+  do {                                        \
+    hipError_t _e = (expr);                   \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+template <typename T>
+pie_status dalloc(pie_op* op, T** p, size_t n) {
+  void* q = nullptr;
+  size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_fail(e, "hipMalloc");
+  }
+  op->allocs.push_back(q);
+  op->bytes += bytes;
+  *p = (T*)q;
+  return PIE_OK;
+}
+
+template <typename T>
+pie_status upload(pie_op* op, T** p, const std::vector<T>& h) {
+  pie_status s = dalloc(op, p, h.size());
+  if (s) return s;
+  if (!h.empty()) HIPCHK(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+  return PIE_OK;
+}
+
+template <typename T>
+std::vector<T> narrow32(const std::vector<int64_t>& v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+// 7-point degree-5 triangle rule (Radon): barycentric nodes and weights.
+void radon7(double bary[7][3], double w[7]) {
+  const double s15 = std::sqrt(15.0);
+  const double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
+  const double w1 = (155.0 - s15) / 1200.0, w2 = (155.0 + s15) / 1200.0;
+  const double b[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {a1, a1, 1 - 2 * a1}, {a1, 1 - 2 * a1, a1},
+                          {1 - 2 * a1, a1, a1},         {a2, a2, 1 - 2 * a2}, {a2, 1 - 2 * a2, a2},
+                          {1 - 2 * a2, a2, a2}};
+  const double ww[7] = {9.0 / 40.0, w1, w1, w1, w2, w2, w2};
+  for (int i = 0; i < 7; ++i) {
+    for (int k = 0; k < 3; ++k) bary[i][k] = b[i][k];
+    w[i] = ww[i];
+  }
+}
+
+double dfact(int n) {  // n!! for odd n >= -1
+  double r = 1.0;
+  for (int i = n; i > 1; i -= 2) r *= i;
+  return r;
+}
+
+template <typename TF>
+std::vector<TF> cast_vec(const std::vector<double>& v) {
+  return std::vector<TF>(v.begin(), v.end());
+}
+
+template <typename TF>
+pie_status upload_tables(pie_op* op, const std::vector<double>& khat, const std::vector<std::vector<double>>& T,
+                         const std::vector<std::vector<double>>& F, const std::vector<std::vector<double>>& Ph) {
+  TF* p = nullptr;
+  pie_status s = upload(op, &p, cast_vec<TF>(khat));
+  if (s) return s;
+  op->dKhat = p;
+  op->dTl.assign(op->L + 1, nullptr);
+  op->dFl.assign(op->L + 1, nullptr);
+  op->dPhl.assign(op->L + 1, nullptr);
+  for (int l = 3; l <= op->L; ++l) {
+    TF* t = nullptr;
+    if ((s = upload(op, &t, cast_vec<TF>(T[l])))) return s;
+    op->dTl[l] = t;
+    if (l < op->L) {
+      TF* f = nullptr;
+      if ((s = upload(op, &f, cast_vec<TF>(F[l])))) return s;
+      op->dFl[l] = f;
+      TF* ph = nullptr;
+      if ((s = upload(op, &ph, cast_vec<TF>(Ph[l])))) return s;
+      op->dPhl[l] = ph;
+    }
+  }
+  return PIE_OK;
+}
+
+pie_status build_operator(pie_op* op, hipStream_t st) {
+  const Mesh& m = *op->mesh;
+  const Tree& t = *op->tree;
+  pie_status s;
+  const int N = op->N, ne = op->ne, nt = op->nt, L = op->L;
+  // ---------------- geometry
+  double bary[7][3], rw[7];
+  radon7(bary, rw);
+  std::vector<double> P(21 * (size_t)nt), W(7 * (size_t)nt);
+  for (int tt = 0; tt < nt; ++tt) {
+    const double* v0 = &m.V[3 * m.T[3 * tt]];
+    const double* v1 = &m.V[3 * m.T[3 * tt + 1]];
+    const double* v2 = &m.V[3 * m.T[3 * tt + 2]];
+    for (int i = 0; i < 7; ++i) {
+      for (int d = 0; d < 3; ++d) P[21 * tt + 3 * i + d] = bary[i][0] * v0[d] + bary[i][1] * v1[d] + bary[i][2] * v2[d];
+      W[7 * tt + i] = m.area[tt] * rw[i];
+    }
+  }
+  if ((s = upload(op, &op->dV, m.V))) return s;
+  if ((s = upload(op, &op->dT, m.T))) return s;
+  if ((s = upload(op, &op->dP, P))) return s;
+  if ((s = upload(op, &op->dW, W))) return s;
+  if ((s = upload(op, &op->dC, m.centroid))) return s;
+  if ((s = upload(op, &op->dN, m.normal))) return s;
+  DevGeo G{op->dV, op->dT, op->dP, op->dW, op->dC, op->dN, (int32_t)nt};
+  // ---------------- basis (box order and canonical)
+  std::vector<int32_t> perm(N), btri(2 * (size_t)N), bfv(2 * (size_t)N, -1);
+  std::vector<double> bs(2 * (size_t)N, 0.0), bd(2 * (size_t)N, 0.0);
+  std::vector<int32_t> ctri(2 * (size_t)ne), cfv(2 * (size_t)ne);
+  std::vector<double> cs(2 * (size_t)ne);
+  for (int e = 0; e < ne; ++e)
+    for (int h = 0; h < 2; ++h) {
+      int tr = m.etri[2 * e + h];
+      double sg = h == 0 ? 1.0 : -1.0;
+      ctri[2 * e + h] = tr;
+      cfv[2 * e + h] = m.efree[2 * e + h];
+      cs[2 * e + h] = sg * m.elen[e] / (2.0 * m.area[tr]);
+    }
+  for (int u = 0; u < N; ++u) {
+    int cu = (int)t.perm[u];
+    perm[u] = cu;
+    if (cu < ne) {
+      for (int h = 0; h < 2; ++h) {
+        int tr = m.etri[2 * cu + h];
+        double sg = h == 0 ? 1.0 : -1.0;
+        btri[2 * u + h] = tr;
+        bfv[2 * u + h] = m.efree[2 * cu + h];
+        bs[2 * u + h] = sg * m.elen[cu] / (2.0 * m.area[tr]);
+        bd[2 * u + h] = sg * m.elen[cu] / m.area[tr];
+      }
+    } else {
+      btri[2 * u] = btri[2 * u + 1] = cu - ne;
+    }
+  }
+  if ((s = upload(op, &op->dPerm, perm))) return s;
+  if ((s = upload(op, &op->dBtri, btri))) return s;
+  if ((s = upload(op, &op->dBfv, bfv))) return s;
+  if ((s = upload(op, &op->dBs, bs))) return s;
+  if ((s = upload(op, &op->dBd, bd))) return s;
+  if ((s = upload(op, &op->dCtri, ctri))) return s;
+  if ((s = upload(op, &op->dCfv, cfv))) return s;
+  if ((s = upload(op, &op->dCs, cs))) return s;
+  DevBasis B{op->dPerm, op->dBtri, op->dBfv, op->dBs, op->dBd, N, ne};
+  // ---------------- near blocks (upper triangle, grouped by row box)
+  const Level& fl = t.lev[L];
+  const int nbL = (int)fl.nb;
+  std::vector<int32_t> box_ptr = narrow32<int32_t>(t.box_ptr);
+  int maxbox = 0;
+  for (int b = 0; b < nbL; ++b) maxbox = std::max(maxbox, box_ptr[b + 1] - box_ptr[b]);
+  if (maxbox > 128) {
+    set_error("a finest box holds more than 128 unknowns; use more levels");
+    return PIE_ERR_UNSUPPORTED;
+  }
+  std::vector<int32_t> ba, bb, prow, pcol, row_ptr(nbL + 1, 0), col_ptr(nbL + 1, 0), col_blk;
+  std::vector<int64_t> boff;
+  std::vector<std::vector<int32_t>> cols(nbL);
+  int64_t off = 0, slot = 0;
+  for (int a = 0; a < nbL; ++a) {
+    for (int64_t k = t.near_ptr[a]; k < t.near_ptr[a + 1]; ++k) {
+      int b = (int)t.near_idx[k];
+      if (b < a) continue;
+      int na = box_ptr[a + 1] - box_ptr[a], nb = box_ptr[b + 1] - box_ptr[b];
+      int id = (int)ba.size();
+      ba.push_back(a);
+      bb.push_back(b);
+      boff.push_back(off);
+      off += (int64_t)na * nb;
+      prow.push_back((int32_t)slot);
+      slot += na;
+      if (b != a) {
+        pcol.push_back((int32_t)slot);
+        slot += nb;
+        cols[b].push_back(id);
+      } else {
+        pcol.push_back(-1);
+      }
+    }
+    row_ptr[a + 1] = (int32_t)ba.size();
+  }
+  for (int b = 0; b < nbL; ++b) {
+    col_ptr[b + 1] = col_ptr[b] + (int32_t)cols[b].size();
+    col_blk.insert(col_blk.end(), cols[b].begin(), cols[b].end());
+  }
+  op->near_entries = off;
+  op->nslots = slot;
+  int32_t *dba, *dbb, *dprow, *dpcol, *dbp, *drp, *dcp, *dcb;
+  int64_t* dbo;
+  if ((s = upload(op, &dba, ba)) || (s = upload(op, &dbb, bb)) || (s = upload(op, &dbo, boff)) ||
+      (s = upload(op, &dprow, prow)) || (s = upload(op, &dpcol, pcol)) || (s = upload(op, &dbp, box_ptr)) ||
+      (s = upload(op, &drp, row_ptr)) || (s = upload(op, &dcp, col_ptr)) || (s = upload(op, &dcb, col_blk)))
+    return s;
+  op->NB = DevNear{(int32_t)ba.size(), dba, dbb, dbo, dprow, dpcol, dbp, drp, dcp, dcb};
+  // ---------------- incidences
+  std::vector<int32_t> iptr(nbL + 1, 0), itri, irwg, ifv, ipulse, uslot(2 * (size_t)N, -1);
+  std::vector<double> irs, ird;
+  int maxinc = 0;
+  for (int b = 0; b < nbL; ++b) {
+    std::map<int, int> local;  // triangle -> incidence index
+    auto get = [&](int tr) {
+      auto it = local.find(tr);
+      if (it != local.end()) return it->second;
+      int j = (int)itri.size();
+      itri.push_back(tr);
+      for (int k = 0; k < 3; ++k) {
+        irwg.push_back(-1);
+        ifv.push_back(0);
+        irs.push_back(0.0);
+        ird.push_back(0.0);
+      }
+      ipulse.push_back(-1);
+      local[tr] = j;
+      return j;
+    };
+    for (int u = box_ptr[b]; u < box_ptr[b + 1]; ++u) {
+      if (perm[u] < ne) {
+        for (int h = 0; h < 2; ++h) {
+          int j = get(btri[2 * u + h]);
+          int k = 0;
+          while (irwg[3 * j + k] >= 0) ++k;  // at most three edges per triangle
+          irwg[3 * j + k] = u;
+          irs[3 * j + k] = bs[2 * u + h];
+          ird[3 * j + k] = bd[2 * u + h];
+          ifv[3 * j + k] = bfv[2 * u + h];
+          uslot[2 * u + h] = 4 * j + k;
+        }
+      } else {
+        int j = get(btri[2 * u]);
+        ipulse[j] = u;
+        uslot[2 * u] = uslot[2 * u + 1] = 4 * j + 3;
+      }
+    }
+    iptr[b + 1] = (int32_t)itri.size();
+    maxinc = std::max(maxinc, iptr[b + 1] - iptr[b]);
+  }
+  op->ninc = (int64_t)itri.size();
+  op->maxpt = 7 * maxinc;
+  int32_t *dip, *dit, *dir, *dif, *dipu, *dus;
+  double *dirs, *dird;
+  if ((s = upload(op, &dip, iptr)) || (s = upload(op, &dit, itri)) || (s = upload(op, &dir, irwg)) ||
+      (s = upload(op, &dirs, irs)) || (s = upload(op, &dird, ird)) || (s = upload(op, &dif, ifv)) ||
+      (s = upload(op, &dipu, ipulse)) || (s = upload(op, &dus, uslot)))
+    return s;
+  op->I = DevInc{dip, dit, dir, dirs, dird, dif, dipu, dus};
+  // ---------------- levels
+  op->lv.assign(L + 1, DevLevel{});
+  op->s_l.assign(L + 1, 0.0);
+  op->kappa_l.assign(L + 1, 0.0);
+  op->d_l.assign(L + 1, 0.0);
+  op->il_pairs = 0;
+  for (int l = 3; l <= L; ++l) {
+    const Level& lvh = t.lev[l];
+    const int nb = (int)lvh.nb;
+    const double d = t.side / (double)(int64_t(1) << (l - 1));
+    op->d_l[l] = d;
+    op->s_l[l] = std::min(1.0, op->k * d / op->xs);
+    op->kappa_l[l] = op->k / op->s_l[l];
+    std::vector<double> cen(3 * (size_t)nb);
+    std::vector<int32_t> oct(nb);
+    for (int b = 0; b < nb; ++b) {
+      for (int c = 0; c < 3; ++c) cen[3 * b + c] = t.origin[c] + ((double)lvh.coords[3 * b + c] + 0.5) * d;
+      oct[b] = (int32_t)((lvh.coords[3 * b] & 1) | ((lvh.coords[3 * b + 1] & 1) << 1) |
+                         ((lvh.coords[3 * b + 2] & 1) << 2));
+    }
+    DevLevel dl{};
+    dl.nb = nb;
+    double* dcen;
+    int32_t *dpar, *doct, *dchild = nullptr, *dilp, *dils, *dilo;
+    if ((s = upload(op, &dcen, cen)) || (s = upload(op, &dpar, narrow32<int32_t>(lvh.parent))) ||
+        (s = upload(op, &doct, oct)) || (s = upload(op, &dilp, narrow32<int32_t>(lvh.il_ptr))) ||
+        (s = upload(op, &dils, narrow32<int32_t>(lvh.il_src))) ||
+        (s = upload(op, &dilo, narrow32<int32_t>(lvh.il_off))))
+      return s;
+    if (l < L && (s = upload(op, &dchild, narrow32<int32_t>(lvh.child_ptr)))) return s;
+    dl.centre = dcen;
+    dl.parent = dpar;
+    dl.octant = doct;
+    dl.child_ptr = dchild;
+    dl.il_ptr = dilp;
+    dl.il_src = dils;
+    dl.il_off = dilo;
+    op->lv[l] = dl;
+    op->il_pairs += (int64_t)lvh.il_src.size();
+  }
+  // ---------------- k-space samples and tables (FP64)
+  const int Q = op->Q, tau = op->tau;
+  std::vector<double> ct, wt;
+  gauss_legendre(op->nth, ct, wt);
+  std::vector<double> khat(3 * (size_t)Q), wq(Q);
+  for (int i = 0; i < op->nth; ++i)
+    for (int j = 0; j < op->nph; ++j) {
+      int q = i * op->nph + j;
+      double ph = 2.0 * kPi * j / op->nph;
+      double st_ = std::sqrt(1.0 - ct[i] * ct[i]);
+      khat[3 * q] = st_ * std::cos(ph);
+      khat[3 * q + 1] = st_ * std::sin(ph);
+      khat[3 * q + 2] = ct[i];
+      wq[q] = wt[i] * (2.0 * kPi / op->nph);
+    }
+  // translation tables T_l[off][q] = (ik/16pi^2) w_q alpha~(khat_q, w = off d_l)
+  std::vector<std::vector<double>> Tt(L + 1), Ft(L + 1), Pht(L + 1);
+  double tmax = 0.0;
+  for (int l = 3; l <= L; ++l) {
+    Tt[l].assign(2 * (size_t)kNumOffsets * Q, 0.0);
+    int id = 0;
+    for (int a = -3; a <= 3; ++a)
+      for (int b = -3; b <= 3; ++b)
+        for (int c = -3; c <= 3; ++c) {
+          if (std::max({std::abs(a), std::abs(b), std::abs(c)}) < 2) continue;
+          double wv[3] = {a * op->d_l[l], b * op->d_l[l], c * op->d_l[l]};
+          double wn = std::sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+          std::vector<double> hk;
+          scaled_hankel(op->k, op->s_l[l], wn, tau, hk);  // k s^t h_t
+          for (int q = 0; q < Q; ++q) {
+            double x = (khat[3 * q] * wv[0] + khat[3 * q + 1] * wv[1] + khat[3 * q + 2] * wv[2]) / wn;
+            std::complex<double> acc(0.0, 0.0);
+            double p0 = 1.0, p1 = x;
+            std::complex<double> it(1.0, 0.0);  // i^t
+            for (int tt = 0; tt <= tau; ++tt) {
+              double Pt = tt == 0 ? 1.0 : (tt == 1 ? x : 0.0);
+              if (tt >= 2) {
+                double p2 = ((2.0 * tt - 1.0) * x * p1 - (tt - 1.0) * p0) / tt;
+                p0 = p1;
+                p1 = p2;
+                Pt = p2;
+              }
+              acc += it * (2.0 * tt + 1.0) * std::complex<double>(hk[2 * tt], hk[2 * tt + 1]) * Pt;
+              it *= std::complex<double>(0.0, 1.0);
+            }
+            std::complex<double> v = std::complex<double>(0.0, 1.0) / (16.0 * kPi * kPi) * wq[q] * acc;
+            Tt[l][2 * ((size_t)id * Q + q)] = v.real();
+            Tt[l][2 * ((size_t)id * Q + q) + 1] = v.imag();
+            tmax = std::max(tmax, std::abs(v));
+          }
+          ++id;
+        }
+    if (l < L) {
+      // inter-level filter F[q][q'] = w_q' sum_l (2l+1)/4pi ratio^l P_l(khat_q.khat_q')
+      const double ratio = op->kappa_l[l] / op->kappa_l[l + 1];
+      Ft[l].assign((size_t)Q * Q, 0.0);
+      for (int q = 0; q < Q; ++q)
+        for (int qq = 0; qq < Q; ++qq) {
+          double x = khat[3 * q] * khat[3 * qq] + khat[3 * q + 1] * khat[3 * qq + 1] + khat[3 * q + 2] * khat[3 * qq + 2];
+          x = std::max(-1.0, std::min(1.0, x));
+          double p0 = 1.0, p1 = x, sum = 1.0 / (4.0 * kPi), rp = 1.0;
+          for (int ll = 1; ll <= tau; ++ll) {
+            double Pl;
+            if (ll == 1) {
+              Pl = x;
+            } else {
+              Pl = ((2.0 * ll - 1.0) * x * p1 - (ll - 1.0) * p0) / ll;
+              p0 = p1;
+              p1 = Pl;
+            }
+            rp *= ratio;
+            sum += (2.0 * ll + 1.0) / (4.0 * kPi) * rp * Pl;
+          }
+          Ft[l][(size_t)q * Q + qq] = sum * wq[qq];
+        }
+      // child phases exp(-i kappa_l khat_q . (C_child - C_parent)), per octant
+      Pht[l].assign(2 * 8 * (size_t)Q, 0.0);
+      const double dc = op->d_l[l] / 2.0;
+      for (int o = 0; o < 8; ++o) {
+        double del[3] = {((o & 1) - 0.5) * dc, (((o >> 1) & 1) - 0.5) * dc, (((o >> 2) & 1) - 0.5) * dc};
+        for (int q = 0; q < Q; ++q) {
+          double th = op->kappa_l[l] * (khat[3 * q] * del[0] + khat[3 * q + 1] * del[1] + khat[3 * q + 2] * del[2]);
+          Pht[l][2 * ((size_t)o * Q + q)] = std::cos(th);
+          Pht[l][2 * ((size_t)o * Q + q) + 1] = -std::sin(th);
+        }
+      }
+    }
+  }
+  if (op->far_prec == PIE_FP32 && !(tmax < 1e30)) {
+    set_error("translation table exceeds the FP32 range");
+    return PIE_ERR_PRECISION;
+  }
+  s = op->far_prec == PIE_FP32 ? upload_tables<float>(op, khat, Tt, Ft, Pht)
+                               : upload_tables<double>(op, khat, Tt, Ft, Pht);
+  if (s) return s;
+  // ---------------- chunk width for the RHS loop (LDS budget 64 KiB)
+  const int tfb = op->far_prec == PIE_FP32 ? 4 : 8;
+  op->rc = 0;
+  for (int rc : {4, 2, 1}) {
+    if (rc > op->max_rhs && rc > 1) continue;
+    size_t a = aggregate_smem(op->maxpt, rc, tfb);
+    size_t r = receive_smem(op->maxpt, Q, rc, rc, tfb);
+    size_t sh = (size_t)2 * Q * 5 * rc * 2 * tfb;
+    if (a <= 65536 && r <= 65536 && sh <= 65536) {
+      op->rc = rc;
+      break;
+    }
+  }
+  if (op->rc == 0) {
+    set_error("a finest box has too many quadrature points for the LDS budget; use more levels");
+    return PIE_ERR_UNSUPPORTED;
+  }
+  // ---------------- workspace
+  const size_t cxf = 2 * (size_t)tfb, cxn = op->near_prec == PIE_FP32 ? 8 : 16;
+  op->dS.assign(L + 1, nullptr);
+  op->dG.assign(L + 1, nullptr);
+  for (int l = 3; l <= L; ++l) {
+    unsigned char *a, *b;
+    size_t n = (size_t)op->lv[l].nb * Q * 5 * op->rc * cxf;
+    if ((s = dalloc(op, &a, n)) || (s = dalloc(op, &b, n))) return s;
+    op->dS[l] = a;
+    op->dG[l] = b;
+  }
+  unsigned char *part, *xb;
+  if ((s = dalloc(op, &part, (size_t)op->nslots * op->rc * cxn)) || (s = dalloc(op, &xb, (size_t)N * op->rc * cxn)))
+    return s;
+  op->dPart = part;
+  op->dXb = xb;
+  if ((s = dalloc(op, &op->dKhR, 3 * (size_t)op->max_rhs)) || (s = dalloc(op, &op->dPolR, 3 * (size_t)op->max_rhs)) ||
+      (s = dalloc(op, &op->dAmpR, 2 * (size_t)op->max_rhs)))
+    return s;
+  // ---------------- near-field fill and diagonal (FP64 arithmetic)
+  unsigned char* nz;
+  if ((s = dalloc(op, &nz, (size_t)op->near_entries * cxn))) return s;
+  op->dNear = nz;
+  hipError_t e = op->near_prec == PIE_FP32 ? launch_near_fill<float>(G, B, op->NB, nz, op->k, op->w2e, st)
+                                           : launch_near_fill<double>(G, B, op->NB, nz, op->k, op->w2e, st);
+  if (e != hipSuccess) return hip_fail(e, "near fill launch");
+  double* diag_box;
+  if ((s = dalloc(op, &diag_box, N)) || (s = dalloc(op, &op->dDiagScale, N))) return s;
+  if ((e = launch_diag(G, B, diag_box, op->k, op->w2e, st)) != hipSuccess) return hip_fail(e, "diag launch");
+  HIPCHK(hipStreamSynchronize(st), "operator setup");
+  std::vector<double> db(N), dsc(N);
+  HIPCHK(hipMemcpy(db.data(), diag_box, N * sizeof(double), hipMemcpyDeviceToHost), "diag copy");
+  for (int u = 0; u < N; ++u) dsc[perm[u]] = db[u] > 0.0 ? 1.0 / std::sqrt(db[u]) : 1.0;
+  HIPCHK(hipMemcpy(op->dDiagScale, dsc.data(), N * sizeof(double), hipMemcpyHostToDevice), "diag copy");
+  return PIE_OK;
+}
+
+hipEvent_t take_event(pie_op* op) {
+  if (!op->ev_pool.empty()) {
+    hipEvent_t e = op->ev_pool.back();
+    op->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs one stage's launches, bracketed by events when profiling is on.
+template <typename F>
+hipError_t stage(pie_op* op, int id, hipStream_t st, F&& launch) {
+  if (!op->prof) return launch();
+  hipEvent_t a = take_event(op), b = take_event(op);
+  if (!a || !b) return launch();
+  (void)hipEventRecord(a, st);
+  hipError_t e = launch();
+  (void)hipEventRecord(b, st);
+  op->ev_used.push_back({id, {a, b}});
+  return e;
+}
+
+DevGeo geo(const pie_op* op) { return DevGeo{op->dV, op->dT, op->dP, op->dW, op->dC, op->dN, (int32_t)op->nt}; }
+DevBasis basis(const pie_op* op) { return DevBasis{op->dPerm, op->dBtri, op->dBfv, op->dBs, op->dBd, op->N, op->ne}; }
+
+// One chunk of <= rc right-hand sides; x, y point at the chunk's first
+// column of [N][ld] arrays.  flags: 1 near, 2 far, 4 adjoint.
+template <typename TF, typename TN>
+pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flags, hipStream_t st) {
+  const int L = op->L, Q = op->Q, ncol = 5 * R;
+  const bool near = flags & 1, far = flags & 2, adj = flags & 4;
+  hipError_t e;
+  if (near) {
+    if ((e = stage(op, PIE_STAGE_PERMUTE, st, [&] {
+           return launch_permute_in<TN>(x, ld, op->dPerm, op->N, R, adj, op->dXb, st);
+         })) != hipSuccess)
+      return hip_fail(e, "permute");
+    if ((e = stage(op, PIE_STAGE_NEAR, st, [&] {
+           return launch_near_spmm<TN>(op->NB, op->dNear, op->dXb, R, op->dPart, R, st);
+         })) != hipSuccess)
+      return hip_fail(e, "near spmm");
+  }
+  const DevGeo G = geo(op);
+  const DevBasis B = basis(op);
+  if (far) {
+    if ((e = stage(op, PIE_STAGE_AGGREGATE, st, [&] {
+           return launch_aggregate<TF>(G, op->I, B, op->lv[L].centre, op->lv[L].nb, op->maxpt, x, ld, R,
+                                       op->dKhat, Q, op->kappa_l[L], op->w2e, adj, op->dS[L], st);
+         })) != hipSuccess)
+      return hip_fail(e, "aggregate");
+    for (int l = L - 1; l >= 3; --l)
+      if ((e = stage(op, PIE_STAGE_SHIFT_UP, st, [&] {
+             return launch_shift_up<TF>(op->lv[l], op->lv[l + 1], op->dS[l + 1], op->dS[l], op->dFl[l],
+                                        op->dPhl[l], Q, ncol, st);
+           })) != hipSuccess)
+        return hip_fail(e, "shift up");
+    for (int l = 3; l <= L; ++l) {
+      const bool hp = l > 3;
+      if ((e = stage(op, PIE_STAGE_TRANSLATE, st, [&] {
+             return launch_translate<TF>(op->lv[l], op->dS[l], op->dTl[l], op->dG[l], hp,
+                                         hp ? op->dG[l - 1] : nullptr, hp ? op->dFl[l - 1] : nullptr,
+                                         hp ? op->dPhl[l - 1] : nullptr, Q, ncol, st);
+           })) != hipSuccess)
+        return hip_fail(e, "translate");
+    }
+  }
+  int rflags = (near ? 1 : 0) | (far ? 2 : 0) | (adj ? 4 : 0);
+  if ((e = stage(op, PIE_STAGE_RECEIVE, st, [&] {
+         return launch_receive<TF, TN>(G, op->I, B, op->NB, op->lv[L].centre, op->lv[L].nb, op->maxpt,
+                                       op->dG[L], op->dKhat, Q, op->kappa_l[L], op->dPart, R, rflags, y, ld,
+                                       st);
+       })) != hipSuccess)
+    return hip_fail(e, "receive");
+  return PIE_OK;
+}
+
+pie_status mvm(pie_op* op, const void* x, void* y, int64_t R, int flags, hipStream_t st) {
+  for (int64_t r0 = 0; r0 < R; r0 += op->rc) {
+    int rw = (int)std::min<int64_t>(op->rc, R - r0);
+    const void* xc = (const cx<double>*)x + r0;
+    void* yc = (cx<double>*)y + r0;
+    pie_status s;
+    if (op->far_prec == PIE_FP32 && op->near_prec == PIE_FP32)
+      s = mvm_chunk<float, float>(op, xc, yc, (int)R, rw, flags, st);
+    else if (op->far_prec == PIE_FP32)
+      s = mvm_chunk<float, double>(op, xc, yc, (int)R, rw, flags, st);
+    else if (op->near_prec == PIE_FP32)
+      s = mvm_chunk<double, float>(op, xc, yc, (int)R, rw, flags, st);
+    else
+      s = mvm_chunk<double, double>(op, xc, yc, (int)R, rw, flags, st);
+    if (s) return s;
+  }
+  return PIE_OK;
+}
+
+pie_status check_op_call(const pie_op* op, const void* x, const void* y, int64_t R) {
+  if (!op || !x || !y) {
+    set_error("null operator or vector");
+    return PIE_ERR_ARG;
+  }
+  if (R < 1 || R > op->max_rhs) {
+    set_error("R must be in [1, max_rhs]");
+    return PIE_ERR_ARG;
+  }
+  if (x == y) {
+    set_error("x and y must not overlap");
+    return PIE_ERR_ARG;
+  }
+  return PIE_OK;
+}
+
+}  // namespace
+
+// =========================================================================
+// C ABI
+// =========================================================================
+extern "C" {
+
+size_t pie_last_error(char* buf, size_t len) {
+  const std::string& s = pie::g_err;
+  if (buf && len) {
+    size_t n = std::min(len - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return s.size();
+}
+
+int32_t pie_version(void) { return 100; }
+
+pie_status pie_mesh_create(const double* V, int64_t nv, const int32_t* T, int64_t nt, pie_mesh** out) {
+  if (!out) {
+    pie::set_error("null output handle");
+    return PIE_ERR_ARG;
+  }
+  *out = nullptr;
+  auto h = std::make_unique<pie_mesh>();
+  pie_status s = pie::build_mesh(V, nv, T, nt, h->m);
+  if (s) return s;
+  *out = h.release();
+  return PIE_OK;
+}
+void pie_mesh_destroy(pie_mesh* m) { delete m; }
+
+pie_status pie_mesh_sizes(const pie_mesh* m, int64_t* nE, int64_t* nT) {
+  if (!m) {
+    pie::set_error("null mesh");
+    return PIE_ERR_ARG;
+  }
+  if (nE) *nE = m->m.ne;
+  if (nT) *nT = m->m.nt;
+  return PIE_OK;
+}
+
+pie_status pie_mesh_edges(const pie_mesh* m, int32_t* edges, int32_t* tri, int32_t* free_vertex) {
+  if (!m) {
+    pie::set_error("null mesh");
+    return PIE_ERR_ARG;
+  }
+  size_t n = 2 * (size_t)m->m.ne;
+  if (edges) std::memcpy(edges, m->m.edge.data(), n * sizeof(int32_t));
+  if (tri) std::memcpy(tri, m->m.etri.data(), n * sizeof(int32_t));
+  if (free_vertex) std::memcpy(free_vertex, m->m.efree.data(), n * sizeof(int32_t));
+  return PIE_OK;
+}
+
+pie_status pie_tree_build(const pie_mesh* m, int32_t levels, pie_tree** out) {
+  if (!m || !out) {
+    pie::set_error("null mesh or output handle");
+    return PIE_ERR_ARG;
+  }
+  *out = nullptr;
+  auto h = std::make_unique<pie_tree>();
+  pie_status s = pie::build_tree(m->m, levels, h->t);
+  if (s) return s;
+  *out = h.release();
+  return PIE_OK;
+}
+void pie_tree_destroy(pie_tree* t) { delete t; }
+
+pie_status pie_tree_query(const pie_tree* th, int32_t what, int32_t level, int64_t* count, int64_t* data) {
+  if (!th || !count) {
+    pie::set_error("null tree or count");
+    return PIE_ERR_ARG;
+  }
+  const pie::Tree& t = th->t;
+  const std::vector<int64_t>* v = nullptr;
+  bool needs_level = what == PIE_TQ_NBOX || what == PIE_TQ_COORDS || what == PIE_TQ_PARENT ||
+                     what == PIE_TQ_IL_PTR || what == PIE_TQ_IL_SRC || what == PIE_TQ_IL_OFF;
+  if (needs_level && (level < 1 || level > t.L)) {
+    pie::set_error("level out of range");
+    return PIE_ERR_ARG;
+  }
+  if ((what == PIE_TQ_IL_PTR || what == PIE_TQ_IL_SRC || what == PIE_TQ_IL_OFF) && level < 3) {
+    pie::set_error("interaction lists exist for levels >= 3");
+    return PIE_ERR_ARG;
+  }
+  switch (what) {
+    case PIE_TQ_NBOX:
+      *count = t.lev[level].nb;
+      return PIE_OK;
+    case PIE_TQ_COORDS: v = &t.lev[level].coords; break;
+    case PIE_TQ_PARENT: v = &t.lev[level].parent; break;
+    case PIE_TQ_PERM: v = &t.perm; break;
+    case PIE_TQ_BOXPTR: v = &t.box_ptr; break;
+    case PIE_TQ_NEAR_PTR: v = &t.near_ptr; break;
+    case PIE_TQ_NEAR_IDX: v = &t.near_idx; break;
+    case PIE_TQ_IL_PTR: v = &t.lev[level].il_ptr; break;
+    case PIE_TQ_IL_SRC: v = &t.lev[level].il_src; break;
+    case PIE_TQ_IL_OFF: v = &t.lev[level].il_off; break;
+    default:
+      pie::set_error("unknown tree query");
+      return PIE_ERR_ARG;
+  }
+  *count = (int64_t)v->size();
+  if (data && !v->empty()) std::memcpy(data, v->data(), v->size() * sizeof(int64_t));
+  return PIE_OK;
+}
+
+void pie_options_default(pie_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->version = 1;
+  o->near_prec = PIE_FP64;
+  o->far_prec = PIE_FP64;
+  o->max_rhs = 1;
+}
+
+pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq_hz, const pie_options* opt,
+                               void* stream, pie_op** out) {
+  if (!m || !t || !opt || !out) {
+    pie::set_error("null argument");
+    return PIE_ERR_ARG;
+  }
+  *out = nullptr;
+  if (opt->version != 1) {
+    pie::set_error("pie_options.version must be 1");
+    return PIE_ERR_ARG;
+  }
+  if (!(freq_hz > 0.0) || !std::isfinite(freq_hz)) {
+    pie::set_error("frequency must be positive and finite");
+    return PIE_ERR_ARG;
+  }
+  if ((opt->near_prec != PIE_FP32 && opt->near_prec != PIE_FP64) ||
+      (opt->far_prec != PIE_FP32 && opt->far_prec != PIE_FP64)) {
+    pie::set_error("precision must be PIE_FP32 or PIE_FP64");
+    return PIE_ERR_ARG;
+  }
+  if (opt->max_rhs < 1 || opt->max_rhs > 4096) {
+    pie::set_error("max_rhs must be in [1, 4096]");
+    return PIE_ERR_ARG;
+  }
+  if (t->t.mesh != &m->m) {
+    pie::set_error("tree was built for a different mesh");
+    return PIE_ERR_ARG;
+  }
+  auto op = std::make_unique<pie_op>();
+  op->mesh = &m->m;
+  op->tree = &t->t;
+  op->freq = freq_hz;
+  op->omega = 2.0 * pie::kPi * freq_hz;
+  op->k = op->omega / pie::kC0;
+  op->w2e = op->omega * op->omega * pie::kEps0;
+  op->near_prec = opt->near_prec;
+  op->far_prec = opt->far_prec;
+  const bool f32 = opt->far_prec == PIE_FP32;
+  op->tau = opt->tau > 0 ? opt->tau : (f32 ? 4 : 6);
+  op->xs = opt->x > 0.0 ? opt->x : (f32 ? 0.15 : 0.07);
+  op->nth = opt->n_theta > 0 ? opt->n_theta : op->tau + 1;
+  op->nph = opt->n_phi > 0 ? opt->n_phi : 2 * op->tau + 2;
+  op->Q = op->nth * op->nph;
+  op->max_rhs = opt->max_rhs;
+  op->L = t->t.L;
+  op->ne = (int)m->m.ne;
+  op->nt = (int)m->m.nt;
+  op->N = op->ne + op->nt;
+  if (op->tau > 20 || op->Q > 1024 || (op->nph & 1)) {
+    pie::set_error("tau <= 20, Q <= 1024 and an even n_phi are required");
+    return PIE_ERR_ARG;
+  }
+  if (m->m.nboundary > 0) {
+    pie::set_error("open surfaces are not supported by this operator");
+    return PIE_ERR_UNSUPPORTED;
+  }
+  const double d3 = t->t.side / 4.0;
+  if (op->k * d3 > 1.0) {
+    pie::set_error("level-3 boxes exceed 1/(2 pi) wavelengths: outside the low-frequency regime");
+    return PIE_ERR_UNSUPPORTED;
+  }
+  // round-off amplification of the sampled translation: (2 tau + 1)!!/(2 x)^tau
+  const double xe = std::min(op->xs, op->k * d3);
+  const double amp = dfact(2 * op->tau + 1) / std::pow(2.0 * std::max(xe, op->xs), op->tau);
+  const double eps = f32 ? 5.96e-8 : 1.11e-16;
+  if (eps * amp > 1e-2) {
+    pie::set_error("tau and x amplify round-off beyond 1e-2 in this far-field precision");
+    return PIE_ERR_PRECISION;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipGetDevice(&op->device), "hipGetDevice");
+  pie_status s = build_operator(op.get(), st);
+  if (s) return s;
+  *out = op.release();
+  return PIE_OK;
+}
+
+void pie_operator_destroy(pie_op* op) { delete op; }
+
+pie_status pie_operator_info(const pie_op* op, int32_t what, int64_t* value) {
+  if (!op || !value) {
+    pie::set_error("null argument");
+    return PIE_ERR_ARG;
+  }
+  switch (what) {
+    case PIE_OI_N: *value = op->N; break;
+    case PIE_OI_Q: *value = op->Q; break;
+    case PIE_OI_TAU: *value = op->tau; break;
+    case PIE_OI_NEAR_BLOCKS: *value = op->NB.nblk; break;
+    case PIE_OI_NEAR_ENTRIES: *value = op->near_entries; break;
+    case PIE_OI_NEAR_BYTES: *value = op->near_entries * (op->near_prec == PIE_FP32 ? 8 : 16); break;
+    case PIE_OI_NBOX_FINEST: *value = op->lv[op->L].nb; break;
+    case PIE_OI_IL_PAIRS: *value = op->il_pairs; break;
+    case PIE_OI_INCIDENCES: *value = op->ninc; break;
+    case PIE_OI_DEVICE_BYTES: *value = (int64_t)op->bytes; break;
+    default:
+      pie::set_error("unknown operator query");
+      return PIE_ERR_ARG;
+  }
+  return PIE_OK;
+}
+
+pie_status pie_operator_level(const pie_op* op, int32_t level, double* s, double* kappa, double* box_side) {
+  if (!op || level < 3 || level > op->L) {
+    pie::set_error("null operator or level out of range");
+    return PIE_ERR_ARG;
+  }
+  if (s) *s = op->s_l[level];
+  if (kappa) *kappa = op->kappa_l[level];
+  if (box_side) *box_side = op->d_l[level];
+  return PIE_OK;
+}
+
+pie_status pie_matvec(pie_op* op, const void* x, void* y, int64_t R, int32_t adjoint, void* stream) {
+  pie_status s = check_op_call(op, x, y, R);
+  if (s) return s;
+  return mvm(op, x, y, R, 3 | (adjoint ? 4 : 0), (hipStream_t)stream);
+}
+
+pie_status pie_matvec_near(pie_op* op, const void* x, void* y, int64_t R, void* stream) {
+  pie_status s = check_op_call(op, x, y, R);
+  if (s) return s;
+  return mvm(op, x, y, R, 1, (hipStream_t)stream);
+}
+
+pie_status pie_matvec_far(pie_op* op, const void* x, void* y, int64_t R, void* stream) {
+  pie_status s = check_op_call(op, x, y, R);
+  if (s) return s;
+  return mvm(op, x, y, R, 2, (hipStream_t)stream);
+}
+
+pie_status pie_profile_enable(pie_op* op, int32_t on) {
+  if (!op) {
+    pie::set_error("null operator");
+    return PIE_ERR_ARG;
+  }
+  for (auto& u : op->ev_used) {
+    op->ev_pool.push_back(u.second.first);
+    op->ev_pool.push_back(u.second.second);
+  }
+  op->ev_used.clear();
+  op->prof = on != 0;
+  return PIE_OK;
+}
+
+pie_status pie_profile_read(pie_op* op, double* ms, int64_t* launches) {
+  if (!op) {
+    pie::set_error("null operator");
+    return PIE_ERR_ARG;
+  }
+  double acc[PIE_NSTAGES] = {0};
+  int64_t cnt[PIE_NSTAGES] = {0};
+  for (auto& u : op->ev_used) {
+    HIPCHK(hipEventSynchronize(u.second.second), "profile sync");
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, u.second.first, u.second.second), "profile elapsed");
+    acc[u.first] += t;
+    cnt[u.first] += 1;
+  }
+  for (int i = 0; i < PIE_NSTAGES; ++i) {
+    if (ms) ms[i] = acc[i];
+    if (launches) launches[i] = cnt[i];
+  }
+  return PIE_OK;
+}
+
+pie_status pie_rhs_planewave(pie_op* op, int64_t R, const double* khat, const double* pol, const double* amp,
+                             int32_t gauge, void* b, void* stream) {
+  if (!op || !khat || !pol || !amp || !b) {
+    pie::set_error("null argument");
+    return PIE_ERR_ARG;
+  }
+  if (R < 1 || R > op->max_rhs || (gauge != 0 && gauge != 1)) {
+    pie::set_error("R must be in [1, max_rhs] and gauge 0 or 1");
+    return PIE_ERR_ARG;
+  }
+  for (int64_t i = 0; i < 3 * R; ++i)
+    if (!std::isfinite(khat[i]) || !std::isfinite(pol[i])) {
+      pie::set_error("non-finite plane-wave direction or polarisation");
+      return PIE_ERR_NONFINITE;
+    }
+  for (int64_t i = 0; i < 2 * R; ++i)
+    if (!std::isfinite(amp[i])) {
+      pie::set_error("non-finite amplitude");
+      return PIE_ERR_NONFINITE;
+    }
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(op->dKhR, khat, 3 * R * sizeof(double), hipMemcpyHostToDevice, st), "rhs copy");
+  HIPCHK(hipMemcpyAsync(op->dPolR, pol, 3 * R * sizeof(double), hipMemcpyHostToDevice, st), "rhs copy");
+  HIPCHK(hipMemcpyAsync(op->dAmpR, amp, 2 * R * sizeof(double), hipMemcpyHostToDevice, st), "rhs copy");
+  hipError_t e = pie::launch_rhs(geo(op), op->dCs, op->dCtri, op->dCfv, op->ne, op->nt, op->dKhR, op->dPolR,
+                                 op->dAmpR, (int)R, gauge, op->k, op->omega, b, st);
+  if (e != hipSuccess) return hip_fail(e, "rhs");
+  HIPCHK(hipStreamSynchronize(st), "rhs");  // host arrays are released on return
+  return PIE_OK;
+}
+
+pie_status pie_farfield(pie_op* op, const void* x, int64_t R, const double* dirs, int64_t nd, void* F,
+                        void* stream) {
+  if (!op || !x || !dirs || !F || nd < 1) {
+    pie::set_error("null argument or no directions");
+    return PIE_ERR_ARG;
+  }
+  if (R < 1 || R > op->max_rhs) {
+    pie::set_error("R must be in [1, max_rhs]");
+    return PIE_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (nd > op->ndirs_cap) {
+    pie_status s = dalloc(op, &op->dDirs, 3 * (size_t)nd);
+    if (s) return s;
+    op->ndirs_cap = nd;
+  }
+  HIPCHK(hipMemcpyAsync(op->dDirs, dirs, 3 * nd * sizeof(double), hipMemcpyHostToDevice, st), "dirs copy");
+  hipError_t e = pie::launch_farfield(geo(op), op->dCs, op->dCtri, op->dCfv, op->ne, x, (int)R, op->dDirs, (int)nd,
+                                      op->k, op->omega, F, st);
+  if (e != hipSuccess) return hip_fail(e, "farfield");
+  HIPCHK(hipStreamSynchronize(st), "farfield");
+  return PIE_OK;
+}
+
+void pie_solve_opts_default(pie_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->version = 1;
+  o->restart = 100;
+  o->maxit = 1000;
+  o->refine = 1;
+  o->tol = 1e-6;
+  o->inner_tol = 0.0;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ GMRES --
+namespace {
+
+// GMRES(m) with CGS2 on the equilibrated operator D Z D for all R columns in
+// lock step; each column keeps its own Hessenberg matrix and rotations and is
+// frozen once its residual estimate meets tol.  xhat (device) is updated.
+pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xhat, int R, const pie_solve_opts& o,
+                              double tol, int adjoint, int* iters, hipStream_t st, cx<double>* work) {
+  const int N = op->N, m = std::max(1, o.restart);
+  const size_t NR = (size_t)N * R;
+  cx<double>* V = work;                    // (m+1) blocks
+  cx<double>* w = V + (size_t)(m + 1) * NR;
+  cx<double>* tmp = w + NR;
+  cx<double>* dh = tmp + NR;               // (m+1) x R
+  double* dn = (double*)(dh + (size_t)(m + 1) * R);
+  std::vector<double> beta(R), nrm(R), inv(R), rhn(R);
+  std::vector<std::complex<double>> H((size_t)R * (m + 1) * m), cs((size_t)R * m), sn((size_t)R * m),
+      g((size_t)R * (m + 1)), h((size_t)(m + 1) * R), h2((size_t)(m + 1) * R);
+  std::vector<int> kused(R, 0);
+  std::vector<char> active(R, 1);
+  hipError_t e;
+  int total = 0;
+  pie_status s;
+  auto dots = [&](int nv, std::vector<std::complex<double>>& out) -> pie_status {
+    if ((e = launch_dots(V, NR, nv, w, N, R, dh, st)) != hipSuccess) return hip_fail(e, "dots");
+    HIPCHK(hipMemcpyAsync(out.data(), dh, (size_t)nv * R * 16, hipMemcpyDeviceToHost, st), "dots copy");
+    HIPCHK(hipStreamSynchronize(st), "dots");
+    return PIE_OK;
+  };
+  while (total < o.maxit) {
+    // r = rhat - A xhat  (A = D Z D)
+    if ((e = launch_scale_rows(xhat, op->dDiagScale, N, R, tmp, st)) != hipSuccess) return hip_fail(e, "scale");
+    if ((s = mvm(op, tmp, w, R, 3 | (adjoint ? 4 : 0), st))) return s;
+    if ((e = launch_scale_rows(w, op->dDiagScale, N, R, w, st)) != hipSuccess) return hip_fail(e, "scale");
+    if ((e = launch_sub(rhat, w, N, R, V, st)) != hipSuccess) return hip_fail(e, "sub");
+    if ((e = launch_norms(V, N, R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
+    HIPCHK(hipMemcpyAsync(beta.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
+    if ((e = launch_norms(rhat, N, R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
+    HIPCHK(hipMemcpyAsync(nrm.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
+    HIPCHK(hipStreamSynchronize(st), "gmres");
+    bool any = false;
+    for (int r = 0; r < R; ++r) {
+      rhn[r] = nrm[r];
+      active[r] = beta[r] > tol * nrm[r];
+      any = any || active[r];
+      inv[r] = beta[r] > 0.0 ? 1.0 / beta[r] : 0.0;
+      kused[r] = 0;
+      for (int j = 0; j <= m; ++j) g[(size_t)r * (m + 1) + j] = 0.0;
+      g[(size_t)r * (m + 1)] = beta[r];
+    }
+    if (!any) break;
+    HIPCHK(hipMemcpyAsync(dn, inv.data(), R * 8, hipMemcpyHostToDevice, st), "inv copy");
+    if ((e = launch_colscale(V, dn, N, R, st)) != hipSuccess) return hip_fail(e, "colscale");
+    int j = 0;
+    for (; j < m && total < o.maxit; ++j) {
+      ++total;
+      cx<double>* vj = V + (size_t)j * NR;
+      if ((e = launch_scale_rows(vj, op->dDiagScale, N, R, tmp, st)) != hipSuccess) return hip_fail(e, "scale");
+      if ((s = mvm(op, tmp, w, R, 3 | (adjoint ? 4 : 0), st))) return s;
+      if ((e = launch_scale_rows(w, op->dDiagScale, N, R, w, st)) != hipSuccess) return hip_fail(e, "scale");
+      // classical Gram-Schmidt, twice
+      if ((s = dots(j + 1, h))) return s;
+      HIPCHK(hipMemcpyAsync(dh, h.data(), (size_t)(j + 1) * R * 16, hipMemcpyHostToDevice, st), "h copy");
+      if ((e = launch_update(w, V, NR, j + 1, dh, N, R, st)) != hipSuccess) return hip_fail(e, "update");
+      if ((s = dots(j + 1, h2))) return s;
+      HIPCHK(hipMemcpyAsync(dh, h2.data(), (size_t)(j + 1) * R * 16, hipMemcpyHostToDevice, st), "h copy");
+      if ((e = launch_update(w, V, NR, j + 1, dh, N, R, st)) != hipSuccess) return hip_fail(e, "update");
+      if ((e = launch_norms(w, N, R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
+      HIPCHK(hipMemcpyAsync(nrm.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
+      HIPCHK(hipStreamSynchronize(st), "gmres");
+      bool any_active = false;
+      for (int r = 0; r < R; ++r) {
+        inv[r] = 0.0;
+        if (!active[r]) continue;
+        std::complex<double>* Hr = &H[(size_t)r * (m + 1) * m];
+        for (int i = 0; i <= j; ++i) Hr[(size_t)i * m + j] = h[(size_t)i * R + r] + h2[(size_t)i * R + r];
+        Hr[(size_t)(j + 1) * m + j] = nrm[r];
+        for (int i = 0; i < j; ++i) {
+          std::complex<double> c = cs[(size_t)r * m + i], sN = sn[(size_t)r * m + i];
+          std::complex<double> a = Hr[(size_t)i * m + j], b = Hr[(size_t)(i + 1) * m + j];
+          Hr[(size_t)i * m + j] = c * a + sN * b;
+          Hr[(size_t)(i + 1) * m + j] = -std::conj(sN) * a + std::conj(c) * b;
+        }
+        std::complex<double> a = Hr[(size_t)j * m + j], b = Hr[(size_t)(j + 1) * m + j];
+        double den = std::sqrt(std::norm(a) + std::norm(b));
+        std::complex<double> c = den > 0 ? a / den : 1.0, sN = den > 0 ? b / den : 0.0;
+        cs[(size_t)r * m + j] = c;
+        sn[(size_t)r * m + j] = sN;
+        Hr[(size_t)j * m + j] = den;
+        Hr[(size_t)(j + 1) * m + j] = 0.0;
+        std::complex<double>* gr = &g[(size_t)r * (m + 1)];
+        gr[j + 1] = -std::conj(sN) * gr[j];
+        gr[j] = std::conj(c) * gr[j];
+        kused[r] = j + 1;
+        active[r] = std::abs(gr[j + 1]) > tol * rhn[r];
+        any_active = any_active || active[r];
+        inv[r] = nrm[r] > 0.0 ? 1.0 / nrm[r] : 0.0;
+      }
+      cx<double>* vn = V + (size_t)(j + 1) * NR;
+      HIPCHK(hipMemcpyAsync(vn, w, NR * 16, hipMemcpyDeviceToDevice, st), "copy");
+      HIPCHK(hipMemcpyAsync(dn, inv.data(), R * 8, hipMemcpyHostToDevice, st), "inv copy");
+      if ((e = launch_colscale(vn, dn, N, R, st)) != hipSuccess) return hip_fail(e, "colscale");
+      // stop the cycle when every column meets tol relative to ||rhat||
+      if (!any_active) break;
+    }
+    // y = H^-1 g per column; xhat += V y (the update kernel subtracts V h,
+    // so h = -y is uploaded)
+    std::vector<std::complex<double>> y((size_t)(m + 1) * R, 0.0);
+    for (int r = 0; r < R; ++r) {
+      int k = kused[r];
+      std::complex<double>* Hr = &H[(size_t)r * (m + 1) * m];
+      std::complex<double>* gr = &g[(size_t)r * (m + 1)];
+      for (int i = k - 1; i >= 0; --i) {
+        std::complex<double> acc = gr[i];
+        for (int l = i + 1; l < k; ++l) acc -= Hr[(size_t)i * m + l] * y[(size_t)l * R + r];
+        y[(size_t)i * R + r] = Hr[(size_t)i * m + i] != 0.0 ? acc / Hr[(size_t)i * m + i] : 0.0;
+      }
+    }
+    for (auto& v : y) v = -v;
+    int kmax = 0;
+    for (int r = 0; r < R; ++r) kmax = std::max(kmax, kused[r]);
+    if (kmax > 0) {
+      HIPCHK(hipMemcpyAsync(dh, y.data(), (size_t)kmax * R * 16, hipMemcpyHostToDevice, st), "y copy");
+      if ((e = launch_update(xhat, V, NR, kmax, dh, N, R, st)) != hipSuccess) return hip_fail(e, "update");
+    }
+    HIPCHK(hipStreamSynchronize(st), "gmres");
+  }
+  *iters = total;
+  return PIE_OK;
+}
+
+}  // namespace
+
+extern "C" pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void* x, int64_t R,
+                                const pie_solve_opts* opts, pie_solve_info* info, void* stream) {
+  pie_status s = check_op_call(op, b, x, R);
+  if (s) return s;
+  pie_solve_opts o;
+  pie_solve_opts_default(&o);
+  if (opts) {
+    if (opts->version != 1) {
+      pie::set_error("pie_solve_opts.version must be 1");
+      return PIE_ERR_ARG;
+    }
+    o = *opts;
+  }
+  if (o.restart < 1 || o.maxit < 1 || o.refine < 1 || !(o.tol > 0.0)) {
+    pie::set_error("restart, maxit, refine must be >= 1 and tol > 0");
+    return PIE_ERR_ARG;
+  }
+  pie_op* rop = res_op ? res_op : op;
+  if (rop->N != op->N || R > rop->max_rhs) {
+    pie::set_error("residual operator does not match");
+    return PIE_ERR_ARG;
+  }
+  const double inner = o.inner_tol > 0.0 ? o.inner_tol : o.tol;
+  hipStream_t st = (hipStream_t)stream;
+  const int N = op->N, m = o.restart;
+  const size_t NR = (size_t)N * R;
+  cx<double>* work = nullptr;
+  size_t wbytes = ((size_t)(m + 1) * NR + 2 * NR) * 16 + (size_t)(m + 1) * R * 16 + R * 16 + 4 * NR * 16;
+  HIPCHK(hipMalloc(&work, wbytes), "solver workspace");
+  std::unique_ptr<void, void (*)(void*)> guard(work, [](void* p) { (void)hipFree(p); });
+  cx<double>* rr = work + ((size_t)(m + 1) * NR + 2 * NR) + (size_t)(m + 1) * R + R;  // after solver area
+  cx<double>* rhat = rr + NR;
+  cx<double>* xh = rhat + NR;
+  cx<double>* zx = xh + NR;
+  double* dn = (double*)(work + (size_t)(m + 1) * NR + 2 * NR + (size_t)(m + 1) * R);
+  cx<double>* X = (cx<double>*)x;
+  hipError_t e;
+  if (!o.use_x0) HIPCHK(hipMemsetAsync(X, 0, NR * 16, st), "zero x");
+  std::vector<double> bn(R), rn(R);
+  if ((e = pie::launch_norms(b, N, (int)R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
+  HIPCHK(hipMemcpyAsync(bn.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
+  int iters = 0, refinements = 0;
+  double relmax = 0.0;
+  for (int k = 0; k < o.refine; ++k) {
+    // residual with the residual operator
+    if ((s = mvm(rop, X, zx, R, 3 | (o.adjoint ? 4 : 0), st))) return s;
+    if ((e = pie::launch_sub(b, zx, N, (int)R, rr, st)) != hipSuccess) return hip_fail(e, "sub");
+    if ((e = pie::launch_norms(rr, N, (int)R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
+    HIPCHK(hipMemcpyAsync(rn.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
+    HIPCHK(hipStreamSynchronize(st), "solve");
+    relmax = 0.0;
+    for (int r = 0; r < R; ++r) relmax = std::max(relmax, bn[r] > 0 ? rn[r] / bn[r] : 0.0);
+    if (relmax <= o.tol) break;
+    ++refinements;
+    if ((e = pie::launch_scale_rows(rr, op->dDiagScale, N, (int)R, rhat, st)) != hipSuccess) return hip_fail(e, "scale");
+    HIPCHK(hipMemsetAsync(xh, 0, NR * 16, st), "zero");
+    int it = 0;
+    if ((s = gmres_equilibrated(op, rhat, xh, (int)R, o, inner, o.adjoint, &it, st, work))) return s;
+    iters += it;
+    if ((e = pie::launch_scale_rows(xh, op->dDiagScale, N, (int)R, xh, st)) != hipSuccess) return hip_fail(e, "scale");
+    std::vector<cx<double>> one(R, cx<double>{1.0, 0.0});
+    HIPCHK(hipMemcpyAsync(dn, one.data(), R * 16, hipMemcpyHostToDevice, st), "one copy");
+    if ((e = pie::launch_axpy_cols(X, xh, dn, N, (int)R, st)) != hipSuccess) return hip_fail(e, "axpy");
+    HIPCHK(hipStreamSynchronize(st), "solve");
+    if (k == o.refine - 1) {
+      if ((s = mvm(rop, X, zx, R, 3 | (o.adjoint ? 4 : 0), st))) return s;
+      if ((e = pie::launch_sub(b, zx, N, (int)R, rr, st)) != hipSuccess) return hip_fail(e, "sub");
+      if ((e = pie::launch_norms(rr, N, (int)R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
+      HIPCHK(hipMemcpyAsync(rn.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
+      HIPCHK(hipStreamSynchronize(st), "solve");
+      relmax = 0.0;
+      for (int r = 0; r < R; ++r) relmax = std::max(relmax, bn[r] > 0 ? rn[r] / bn[r] : 0.0);
+    }
+  }
+  if (info) {
+    info->iterations = iters;
+    info->refinements = refinements;
+    info->rel_residual = relmax;
+  }
+  return relmax <= o.tol ? PIE_OK : PIE_WARN_NOT_CONVERGED;
+}

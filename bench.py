@@ -77,6 +77,21 @@ def time_mvm(op, x, y, steps, warmup, profile):
     return s0.elapsed_time(s1) / steps, wall / steps, stages
 
 
+def time_near_only(op, x, y, steps):
+    """Near-field-only MVMs (same SpMM kernel and launch shape, no
+    concurrent far-field work) with stage events: standalone SpMM time."""
+    import torch
+    op.matvec_near(x, y)
+    torch.cuda.synchronize()
+    op.profile(True)
+    for _ in range(steps):
+        op.matvec_near(x, y)
+    torch.cuda.synchronize()
+    st = op.profile_read()
+    op.profile(False)
+    return st["near"][0] / max(1, st["near"][1])
+
+
 def cpu_baseline_leg(w, x, rows):
     """The FP64 CPU oracle on a bounded sample: K rows of the dense PIE
     matrix are filled and applied to x (one core of NumPy).  Returns the
@@ -133,9 +148,11 @@ def main():
     for m in modes:
         y = torch.empty_like(x)
         ms, wall, stages = time_mvm(ops[m], x, y, args.steps, args.warmup, profile=True)
-        res[m] = dict(ms=ms, wall_ms=wall * 1e3, stages=stages)
+        res[m] = dict(ms=ms, wall_ms=wall * 1e3, stages=stages,
+                      near_alone_ms=time_near_only(ops[m], x, y, args.steps))
         log(f"[bench] {m}: {ms:.4f} ms/MVM  stages(ms/launch) " +
-            " ".join(f"{k}={v[0] / max(1, v[1]):.4f}" for k, v in stages.items() if v[1]))
+            " ".join(f"{k}={v[0] / max(1, v[1]):.4f}" for k, v in stages.items() if v[1]) +
+            f"  near alone {res[m]['near_alone_ms']:.4f}")
     # --- accuracy gate on sampled rows (the oracle leg provides the reference)
     cpu = None
     if not args.no_cpu:
@@ -167,7 +184,10 @@ def main():
     near_bytes = op.info("NEAR_BYTES") + 2 * N * R * 8
     per_launch_ms = st["near"][0] / max(1, st["near"][1])
     roof = dict(bound="hbm", kernel="near_spmm", achieved=near_bytes / (per_launch_ms * 1e-3) / 1e9,
-                peak=HBM_PEAK_GBS, unit="GB/s", traffic=None)
+                peak=HBM_PEAK_GBS, unit="GB/s", traffic=None,
+                bytes_per_launch=near_bytes, ms_per_launch=per_launch_ms,
+                standalone_ms_per_launch=res[head]["near_alone_ms"],
+                standalone_frac=near_bytes / (res[head]["near_alone_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
     roof["frac"] = roof["achieved"] / roof["peak"]
     out = {
         "metric": "MLFMA matvec unknown*RHS/s at <=1e-3 rel err; batched FP32 vs plain FP64",
@@ -187,6 +207,7 @@ def main():
         "modes": {m: {"ms_per_mvm": res[m]["ms"], "unknown_rhs_per_s": N * R / (res[m]["ms"] * 1e-3),
                       "max_block_err": (max(res[m]["err"].values()) if "err" in res[m] else None),
                       "gate_1e-3": gate[m],
+                      "near_standalone_ms": res[m]["near_alone_ms"],
                       "stage_ms_per_launch": {k: v[0] / max(1, v[1]) for k, v in res[m]["stages"].items()}}
                   for m in modes},
         "speedup_vs_fp64": res["fp64"]["ms"] / res[head]["ms"],

@@ -226,26 +226,20 @@ __global__ void k_diag(DevGeo G, DevBasis B, double* diag_abs, double k, double 
 // SpMM over the stored upper-triangle blocks.  One workgroup per block
 // (a, b): the row part r = Z_ab x_b goes to the partial slot of the rows, and
 // for a < b the transposed part c = Z_ab^T x_a (Z is symmetric) to the slot
-// of the columns.  Each wave owns rows i = wave, wave+4, ...; lanes run over
-// columns; row sums are wave reductions, column sums are lane-private and
-// combined across the four waves in a fixed order.  No atomics: the result
-// is bitwise reproducible.
+// of the columns.  The block is streamed through LDS in row panels with
+// coalesced loads; threads 0..127 form row sums (one row each), threads
+// 128..255 column sums (one column each, carried across panels).  Every sum
+// runs in a fixed order, without atomics: the result is bitwise reproducible.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 template <typename TN, int RC>
 __global__ void __launch_bounds__(256) k_near_spmm(DevNear NB, const cx<TN>* __restrict__ Z,
                                                    const cx<TN>* __restrict__ xb, int ldx,
                                                    cx<TN>* __restrict__ part, int R) {
-  constexpr int MAXB = 128;  // max unknowns per box handled (checked on the host)
+  constexpr int MAXB = 128;  // max unknowns per box (checked on the host)
+  constexpr int ZCAP = sizeof(TN) == 4 ? 4096 : 2048;  // 32 KiB panel
+  __shared__ cx<TN> Zs[ZCAP];
   __shared__ cx<TN> xa_s[MAXB * RC];
-  __shared__ cx<TN> xbb_s[MAXB * RC];
-  __shared__ cx<TN> col_s[4][MAXB * RC];
+  __shared__ cx<TN> xb_s[MAXB * RC];
   const int blk = blockIdx.x;
   const int a = NB.blk_a[blk], b = NB.blk_b[blk];
   const int u0 = NB.box_ptr[a], na = NB.box_ptr[a + 1] - u0;
@@ -253,67 +247,60 @@ __global__ void __launch_bounds__(256) k_near_spmm(DevNear NB, const cx<TN>* __r
   const bool offdiag = a != b;
   for (int e = threadIdx.x; e < nb * R; e += blockDim.x) {
     int j = e / R, r = e - j * R;
-    xbb_s[j * RC + r] = xb[(size_t)(v0 + j) * ldx + r];
+    xb_s[j * RC + r] = xb[(size_t)(v0 + j) * ldx + r];
   }
   if (offdiag)
     for (int e = threadIdx.x; e < na * R; e += blockDim.x) {
       int i = e / R, r = e - i * R;
       xa_s[i * RC + r] = xb[(size_t)(u0 + i) * ldx + r];
     }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const cx<TN>* Zb = Z + NB.blk_off[blk];
-  cx<TN> cacc[2][RC];
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int r = 0; r < RC; ++r) cacc[h][r] = mk<TN>(0, 0);
   cx<TN>* prow = part + (size_t)NB.prow[blk] * R;
-  for (int i = wave; i < na; i += 4) {
-    cx<TN> racc[RC];
+  const int tid = threadIdx.x;
+  const int jc = tid - 128;
+  cx<TN> cacc[RC];
 #pragma unroll
-    for (int r = 0; r < RC; ++r) racc[r] = mk<TN>(0, 0);
+  for (int r = 0; r < RC; ++r) cacc[r] = mk<TN>(0, 0);
+  int rpp = ZCAP / nb;
+  if (rpp > 128) rpp = 128;
+  for (int i0 = 0; i0 < na; i0 += rpp) {
+    const int i1 = i0 + rpp < na ? i0 + rpp : na;
+    const int cnt = (i1 - i0) * nb;
+    __syncthreads();
+    const cx<TN>* src = Zb + (size_t)i0 * nb;
+    for (int e = tid; e < cnt; e += blockDim.x) Zs[e] = src[e];
+    __syncthreads();
+    if (tid < 128) {
+      const int i = i0 + tid;
+      if (i < i1) {
+        cx<TN> racc[RC];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      int j = lane + 64 * h;
-      if (j < nb) {
-        cx<TN> z = Zb[(size_t)i * nb + j];
+        for (int r = 0; r < RC; ++r) racc[r] = mk<TN>(0, 0);
+        const cx<TN>* zr = Zs + (size_t)(i - i0) * nb;
+        for (int j = 0; j < nb; ++j) {
+          const cx<TN> z = zr[j];
 #pragma unroll
-        for (int r = 0; r < RC; ++r) {
-          if (r < R) {
-            cfma(racc[r], z, xbb_s[j * RC + r]);
-            if (offdiag) cfma(cacc[h][r], z, xa_s[i * RC + r]);
-          }
+          for (int r = 0; r < RC; ++r)
+            if (r < R) cfma(racc[r], z, xb_s[j * RC + r]);
         }
-      }
-    }
 #pragma unroll
-    for (int r = 0; r < RC; ++r) {
-      if (r < R) {
-        TN re = wave_sum(racc[r].re), im = wave_sum(racc[r].im);
-        if (lane == 0) prow[(size_t)i * R + r] = mk(re, im);
+        for (int r = 0; r < RC; ++r)
+          if (r < R) prow[(size_t)i * R + r] = racc[r];
+      }
+    } else if (offdiag && jc < nb) {
+      for (int i = i0; i < i1; ++i) {
+        const cx<TN> z = Zs[(size_t)(i - i0) * nb + jc];
+#pragma unroll
+        for (int r = 0; r < RC; ++r)
+          if (r < R) cfma(cacc[r], z, xa_s[i * RC + r]);
       }
     }
   }
-  if (offdiag) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      int j = lane + 64 * h;
-      if (j < nb)
-#pragma unroll
-        for (int r = 0; r < RC; ++r)
-          if (r < R) col_s[wave][j * RC + r] = cacc[h][r];
-    }
-    __syncthreads();
+  if (offdiag && tid >= 128 && jc < nb) {
     cx<TN>* pcol = part + (size_t)NB.pcol[blk] * R;
-    for (int e = threadIdx.x; e < nb * R; e += blockDim.x) {
-      int j = e / R, r = e - j * R;
-      cx<TN> s = col_s[0][j * RC + r];
-      s = s + col_s[1][j * RC + r];
-      s = s + col_s[2][j * RC + r];
-      s = s + col_s[3][j * RC + r];
-      pcol[(size_t)j * R + r] = s;
-    }
+#pragma unroll
+    for (int r = 0; r < RC; ++r)
+      if (r < R) pcol[(size_t)jc * R + r] = cacc[r];
   }
 }
 

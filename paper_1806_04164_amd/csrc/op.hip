@@ -36,6 +36,9 @@ struct pie_op {
   double xs = 0;
   int max_rhs = 1, rc = 1, L = 0, N = 0, ne = 0, nt = 0;
   int maxpt = 0;
+  int nsplit = 1;  // aggregation point-loop split (fixed per operator: RHS-batch-independent order)
+  int short_phase = 0;  // 1: every pattern phase |kappa khat.(r - C)| is within the short Taylor bound
+  double theta_max = 0.0;
   // device geometry
   double *dV = nullptr, *dP = nullptr, *dW = nullptr, *dC = nullptr, *dN = nullptr;
   int32_t* dT = nullptr;
@@ -47,7 +50,10 @@ struct pie_op {
   // near field
   pie::DevNear NB{};
   void* dNear = nullptr;
-  int64_t near_entries = 0, nslots = 0;
+  int64_t near_entries = 0, near_stored = 0, nslots = 0;
+  // second stream for the near field, forked from and joined to the caller's
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // incidences
   pie::DevInc I{};
   int64_t ninc = 0;
@@ -57,9 +63,10 @@ struct pie_op {
   int64_t il_pairs = 0;
   // tables in far precision
   void* dKhat = nullptr;
-  std::vector<void*> dTl, dFl, dPhl;
+  std::vector<void*> dTl, dFl, dFtl, dPhl;
   // workspace
   std::vector<void*> dS, dG;
+  void* dY = nullptr;  // per-child filtered patterns of the shift-up (finest-level sized)
   void* dPart = nullptr;
   void* dXb = nullptr;
   double* dDiagScale = nullptr;  // |Z_uu|^-1/2, canonical order
@@ -72,6 +79,9 @@ struct pie_op {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
   ~pie_op() {
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     for (auto& u : ev_used) {
       (void)hipEventDestroy(u.second.first);
       (void)hipEventDestroy(u.second.second);
@@ -159,6 +169,7 @@ pie_status upload_tables(pie_op* op, const std::vector<double>& khat, const std:
   op->dKhat = p;
   op->dTl.assign(op->L + 1, nullptr);
   op->dFl.assign(op->L + 1, nullptr);
+  op->dFtl.assign(op->L + 1, nullptr);
   op->dPhl.assign(op->L + 1, nullptr);
   for (int l = 3; l <= op->L; ++l) {
     TF* t = nullptr;
@@ -168,6 +179,13 @@ pie_status upload_tables(pie_op* op, const std::vector<double>& khat, const std:
       TF* f = nullptr;
       if ((s = upload(op, &f, cast_vec<TF>(F[l])))) return s;
       op->dFl[l] = f;
+      const int Q = op->Q;
+      std::vector<double> Ftr((size_t)Q * Q);
+      for (int a = 0; a < Q; ++a)
+        for (int b = 0; b < Q; ++b) Ftr[(size_t)b * Q + a] = F[l][(size_t)a * Q + b];
+      TF* ft = nullptr;
+      if ((s = upload(op, &ft, cast_vec<TF>(Ftr)))) return s;
+      op->dFtl[l] = ft;
       TF* ph = nullptr;
       if ((s = upload(op, &ph, cast_vec<TF>(Ph[l])))) return s;
       op->dPhl[l] = ph;
@@ -252,7 +270,7 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   std::vector<int32_t> ba, bb, prow, pcol, row_ptr(nbL + 1, 0), col_ptr(nbL + 1, 0), col_blk;
   std::vector<int64_t> boff;
   std::vector<std::vector<int32_t>> cols(nbL);
-  int64_t off = 0, slot = 0;
+  int64_t off = 0, slot = 0, entries = 0;
   for (int a = 0; a < nbL; ++a) {
     for (int64_t k = t.near_ptr[a]; k < t.near_ptr[a + 1]; ++k) {
       int b = (int)t.near_idx[k];
@@ -262,7 +280,8 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
       ba.push_back(a);
       bb.push_back(b);
       boff.push_back(off);
-      off += (int64_t)na * nb;
+      off += ((int64_t)na * nb + 3) & ~int64_t(3);  // 4-entry aligned blocks
+      entries += (int64_t)na * nb;
       prow.push_back((int32_t)slot);
       slot += na;
       if (b != a) {
@@ -279,7 +298,8 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     col_ptr[b + 1] = col_ptr[b] + (int32_t)cols[b].size();
     col_blk.insert(col_blk.end(), cols[b].begin(), cols[b].end());
   }
-  op->near_entries = off;
+  op->near_stored = off;
+  op->near_entries = entries;
   op->nslots = slot;
   int32_t *dba, *dbb, *dprow, *dpcol, *dbp, *drp, *dcp, *dcb;
   int64_t* dbo;
@@ -378,6 +398,24 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     dl.il_off = dilo;
     op->lv[l] = dl;
     op->il_pairs += (int64_t)lvh.il_src.size();
+  }
+  // ---------------- largest pattern phase |kappa_L khat.(r_i - C_box)| <= kappa_L |r_i - C_box|
+  {
+    const Level& fl2 = t.lev[L];
+    const double dL = op->d_l[L];
+    double rmax = 0.0;
+    for (int b = 0; b < nbL; ++b) {
+      double c[3];
+      for (int d = 0; d < 3; ++d) c[d] = t.origin[d] + ((double)fl2.coords[3 * b + d] + 0.5) * dL;
+      for (int j = iptr[b]; j < iptr[b + 1]; ++j)
+        for (int i = 0; i < 7; ++i) {
+          const double* pp = &P[21 * (size_t)itri[j] + 3 * i];
+          double dx = pp[0] - c[0], dy = pp[1] - c[1], dz = pp[2] - c[2];
+          rmax = std::max(rmax, std::sqrt(dx * dx + dy * dy + dz * dz));
+        }
+    }
+    op->theta_max = op->kappa_l[L] * rmax * (1.0 + 1e-12);
+    op->short_phase = op->theta_max <= (op->far_prec == PIE_FP32 ? 0.2 : 0.1) ? 1 : 0;
   }
   // ---------------- k-space samples and tables (FP64)
   const int Q = op->Q, tau = op->tau;
@@ -479,7 +517,7 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   op->rc = 0;
   for (int rc : {4, 2, 1}) {
     if (rc > op->max_rhs && rc > 1) continue;
-    size_t a = aggregate_smem(op->maxpt, rc, tfb);
+    size_t a = aggregate_smem(op->maxpt, Q, 1, rc, tfb);
     size_t r = receive_smem(op->maxpt, Q, rc, rc, tfb);
     size_t sh = (size_t)2 * Q * 5 * rc * 2 * tfb;
     if (a <= 65536 && r <= 65536 && sh <= 65536) {
@@ -490,6 +528,11 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   if (op->rc == 0) {
     set_error("a finest box has too many quadrature points for the LDS budget; use more levels");
     return PIE_ERR_UNSUPPORTED;
+  }
+  {
+    const int rcm = op->rc <= 1 ? 1 : (op->rc <= 2 ? 2 : 4);
+    op->nsplit = 256 / Q < 1 ? 1 : 256 / Q;
+    while (op->nsplit > 1 && aggregate_smem(op->maxpt, Q, op->nsplit, rcm, tfb) > 65536) --op->nsplit;
   }
   // ---------------- workspace
   const size_t cxf = 2 * (size_t)tfb, cxn = op->near_prec == PIE_FP32 ? 8 : 16;
@@ -502,6 +545,11 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     op->dS[l] = a;
     op->dG[l] = b;
   }
+  {
+    unsigned char* yw;
+    if ((s = dalloc(op, &yw, (size_t)op->lv[L].nb * Q * 5 * op->rc * cxf))) return s;
+    op->dY = yw;
+  }
   unsigned char *part, *xb;
   if ((s = dalloc(op, &part, (size_t)op->nslots * op->rc * cxn)) || (s = dalloc(op, &xb, (size_t)N * op->rc * cxn)))
     return s;
@@ -512,7 +560,7 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     return s;
   // ---------------- near-field fill and diagonal (FP64 arithmetic)
   unsigned char* nz;
-  if ((s = dalloc(op, &nz, (size_t)op->near_entries * cxn))) return s;
+  if ((s = dalloc(op, &nz, (size_t)op->near_stored * cxn))) return s;
   op->dNear = nz;
   hipError_t e = op->near_prec == PIE_FP32 ? launch_near_fill<float>(G, B, op->NB, nz, op->k, op->w2e, st)
                                            : launch_near_fill<double>(G, B, op->NB, nz, op->k, op->w2e, st);
@@ -559,31 +607,40 @@ DevBasis basis(const pie_op* op) { return DevBasis{op->dPerm, op->dBtri, op->dBf
 // column of [N][ld] arrays.  flags: 1 near, 2 far, 4 adjoint.
 template <typename TF, typename TN>
 pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flags, hipStream_t st) {
-  const int L = op->L, Q = op->Q, ncol = 5 * R;
+  const int L = op->L, Q = op->Q;
   const bool near = flags & 1, far = flags & 2, adj = flags & 4;
   hipError_t e;
+  // The near field runs on the operator's side stream, overlapping the far
+  // field's chain on the caller's stream; reception joins the two.
+  const bool fork = near && far;
+  hipStream_t sn = fork ? op->side : st;
+  if (fork) {
+    HIPCHK(hipEventRecord(op->ev_fork, st), "fork");
+    HIPCHK(hipStreamWaitEvent(sn, op->ev_fork, 0), "fork");
+  }
   if (near) {
-    if ((e = stage(op, PIE_STAGE_PERMUTE, st, [&] {
-           return launch_permute_in<TN>(x, ld, op->dPerm, op->N, R, adj, op->dXb, st);
+    if ((e = stage(op, PIE_STAGE_PERMUTE, sn, [&] {
+           return launch_permute_in<TN>(x, ld, op->dPerm, op->N, R, adj, op->dXb, sn);
          })) != hipSuccess)
       return hip_fail(e, "permute");
-    if ((e = stage(op, PIE_STAGE_NEAR, st, [&] {
-           return launch_near_spmm<TN>(op->NB, op->dNear, op->dXb, R, op->dPart, R, st);
+    if ((e = stage(op, PIE_STAGE_NEAR, sn, [&] {
+           return launch_near_spmm<TN>(op->NB, op->dNear, op->dXb, R, op->dPart, R, sn);
          })) != hipSuccess)
       return hip_fail(e, "near spmm");
   }
+  if (fork) HIPCHK(hipEventRecord(op->ev_join, sn), "join");
   const DevGeo G = geo(op);
   const DevBasis B = basis(op);
   if (far) {
     if ((e = stage(op, PIE_STAGE_AGGREGATE, st, [&] {
            return launch_aggregate<TF>(G, op->I, B, op->lv[L].centre, op->lv[L].nb, op->maxpt, x, ld, R,
-                                       op->dKhat, Q, op->kappa_l[L], op->w2e, adj, op->dS[L], st);
+                                       op->dKhat, Q, op->kappa_l[L], op->w2e, adj, op->nsplit, op->short_phase, op->dS[L], st);
          })) != hipSuccess)
       return hip_fail(e, "aggregate");
     for (int l = L - 1; l >= 3; --l)
       if ((e = stage(op, PIE_STAGE_SHIFT_UP, st, [&] {
-             return launch_shift_up<TF>(op->lv[l], op->lv[l + 1], op->dS[l + 1], op->dS[l], op->dFl[l],
-                                        op->dPhl[l], Q, ncol, st);
+             return launch_shift_up<TF>(op->lv[l], op->lv[l + 1], op->dS[l + 1], op->dS[l], op->dFtl[l],
+                                        op->dPhl[l], Q, R, op->dY, st);
            })) != hipSuccess)
         return hip_fail(e, "shift up");
     for (int l = 3; l <= L; ++l) {
@@ -591,24 +648,29 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
       if ((e = stage(op, PIE_STAGE_TRANSLATE, st, [&] {
              return launch_translate<TF>(op->lv[l], op->dS[l], op->dTl[l], op->dG[l], hp,
                                          hp ? op->dG[l - 1] : nullptr, hp ? op->dFl[l - 1] : nullptr,
-                                         hp ? op->dPhl[l - 1] : nullptr, Q, ncol, st);
+                                         hp ? op->dPhl[l - 1] : nullptr, Q, R, st);
            })) != hipSuccess)
         return hip_fail(e, "translate");
     }
   }
   int rflags = (near ? 1 : 0) | (far ? 2 : 0) | (adj ? 4 : 0);
+  if (fork) HIPCHK(hipStreamWaitEvent(st, op->ev_join, 0), "join");
   if ((e = stage(op, PIE_STAGE_RECEIVE, st, [&] {
          return launch_receive<TF, TN>(G, op->I, B, op->NB, op->lv[L].centre, op->lv[L].nb, op->maxpt,
-                                       op->dG[L], op->dKhat, Q, op->kappa_l[L], op->dPart, R, rflags, y, ld,
-                                       st);
+                                       op->dG[L], op->dKhat, Q, op->kappa_l[L], op->dPart, R, rflags,
+                                       op->short_phase, y, ld, st);
        })) != hipSuccess)
     return hip_fail(e, "receive");
   return PIE_OK;
 }
 
 pie_status mvm(pie_op* op, const void* x, void* y, int64_t R, int flags, hipStream_t st) {
-  for (int64_t r0 = 0; r0 < R; r0 += op->rc) {
-    int rw = (int)std::min<int64_t>(op->rc, R - r0);
+  // chunks of exactly 4, 2 or 1 right-hand sides (compile-time widths in
+  // the pattern kernels); each column's arithmetic is the same in any chunk
+  int64_t r0 = 0;
+  while (r0 < R) {
+    const int64_t rem = R - r0;
+    const int rw = (rem >= 4 && op->rc >= 4) ? 4 : ((rem >= 2 && op->rc >= 2) ? 2 : 1);
     const void* xc = (const cx<double>*)x + r0;
     void* yc = (cx<double>*)y + r0;
     pie_status s;
@@ -621,6 +683,7 @@ pie_status mvm(pie_op* op, const void* x, void* y, int64_t R, int flags, hipStre
     else
       s = mvm_chunk<double, double>(op, xc, yc, (int)R, rw, flags, st);
     if (s) return s;
+    r0 += rw;
   }
   return PIE_OK;
 }
@@ -829,6 +892,9 @@ pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq
   }
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipGetDevice(&op->device), "hipGetDevice");
+  HIPCHK(hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking), "side stream");
+  HIPCHK(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming), "fork event");
+  HIPCHK(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming), "join event");
   pie_status s = build_operator(op.get(), st);
   if (s) return s;
   *out = op.release();

@@ -71,7 +71,7 @@ __device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c)
 //   FP64, NT = 9 (through th^17): |th| <= 0.5, omitted 0.5^18/18! ~ 6e-22
 //   FP32, NT = 4 (through th^7):  |th| <= 0.2, omitted 0.2^8/8!  ~ 6e-11
 //   FP32, NT = 6 (through th^11): |th| <= 0.5, omitted 0.5^12/12! ~ 5e-13
-// Arguments beyond the bound fall back to the library sincos.
+// Operators whose bound exceeds 1/2 use the library sincos throughout.
 template <typename T, int NT>
 struct PhaseLimit;
 template <> struct PhaseLimit<double, 5> { static constexpr double v = 0.1; };
@@ -91,22 +91,25 @@ __device__ __forceinline__ constexpr double inv_fact_odd(int k) {
        : k == 7 ? 1.0 / 1307674368000.0 : 1.0 / 355687428096000.0;
 }
 
+// NT = 0: library sincos (used when the host bound exceeds 1/2); NT > 0:
+// the polynomial only -- the host guarantees |th| within the bound, so there
+// is no run-time fallback (and no register cost for one).
 template <typename T, int NT>
 __device__ __forceinline__ void phase(T th, T* s, T* c) {
-  if (fabs(th) > PhaseLimit<T, NT>::v) {
+  if constexpr (NT == 0) {
     sincos_t<T>(th, s, c);
-    return;
-  }
-  const T t2 = -th * th;
-  T cc = (T)inv_fact_even(NT - 1);
-  T ss = (T)inv_fact_odd(NT - 1);
+  } else {
+    const T t2 = -th * th;
+    T cc = (T)inv_fact_even(NT - 1);
+    T ss = (T)inv_fact_odd(NT - 1);
 #pragma unroll
-  for (int k = NT - 2; k >= 0; --k) {
-    cc = fma(cc, t2, (T)inv_fact_even(k));
-    ss = fma(ss, t2, (T)inv_fact_odd(k));
+    for (int k = NT - 2; k >= 0; --k) {
+      cc = fma(cc, t2, (T)inv_fact_even(k));
+      ss = fma(ss, t2, (T)inv_fact_odd(k));
+    }
+    *c = cc;
+    *s = ss * th;
   }
-  *c = cc;
-  *s = ss * th;
 }
 
 // Workgroup -> box index with consecutive boxes (Morton order, i.e. spatial
@@ -143,18 +146,23 @@ struct DevBasis {
   int32_t N, ne;
 };
 
-// Stored near-field blocks (a <= b, Morton box indices), row-major n_a x n_b.
+// Stored near-field blocks (a <= b, Morton box indices), row-major n_a x n_b,
+// processed as row-panel tasks of at most one LDS panel each.
 struct DevNear {
   int32_t nblk;
   const int32_t* blk_a;
   const int32_t* blk_b;
   const int64_t* blk_off;   // entry offset of each block
   const int32_t* prow;      // partial-sum slot of the block's rows
-  const int32_t* pcol;      // partial-sum slot of the block's columns (a < b)
+  int32_t ntask;
+  const int32_t* t_blk;     // task -> block
+  const int32_t* t_i0;      // task row range [i0, i1) within the block
+  const int32_t* t_i1;
+  const int32_t* pcol;      // task -> partial-sum slot of its column sums (a < b)
   const int32_t* box_ptr;   // [nbL+1] box-order unknown ranges
   const int32_t* row_ptr;   // [nbL+1] blocks whose a is the box
   const int32_t* col_ptr;   // [nbL+1] into col_blk
-  const int32_t* col_blk;   // blocks (a < b) whose b is the box
+  const int32_t* col_blk;   // tasks of blocks (a < b) whose b is the box
 };
 
 // One tree level.

@@ -267,6 +267,7 @@ __global__ void __launch_bounds__(256) k_receive(DevGeo G, DevInc I, DevBasis B,
 #pragma unroll
       for (int c = 0; c < ncol; ++c) acc[c] = mk<TF>(0, 0);
       const TF ox = poff[3 * p], oy = poff[3 * p + 1], oz = poff[3 * p + 2];
+#pragma unroll 2
       for (int q = 0; q < Q; ++q) {
         const TF* k4 = kh + 4 * q;
         cx<TF> gq[ncol];
@@ -295,6 +296,7 @@ __global__ void __launch_bounds__(256) k_receive(DevGeo G, DevInc I, DevBasis B,
     cx<double> val = mk(0.0, 0.0);
     if (do_far) {
       if (cu < B.ne) {
+#pragma unroll 1
         for (int h = 0; h < 2; ++h) {
           const int slot = I.uslot[2 * u + h];
           const int j = slot >> 2, k = slot & 3;
@@ -302,6 +304,7 @@ __global__ void __launch_bounds__(256) k_receive(DevGeo G, DevInc I, DevBasis B,
           const double s = I.rs[3 * j + k], d = I.rd[3 * j + k];
           const double* pv = G.V + 3 * I.rfv[3 * j + k];
           const cx<TF>* fp = fld + (size_t)(j - j0) * 7 * ncol;
+#pragma unroll 1
           for (int i = 0; i < 7; ++i) {
             const double* P = G.P + 21 * t + 3 * i;
             const cx<TF>* f = fp + (size_t)i * ncol;
@@ -378,14 +381,16 @@ static void agg_launch(const DevGeo& G, const DevInc& I, const DevBasis& B, cons
 template <typename TF>
 hipError_t launch_aggregate(const DevGeo& G, const DevInc& I, const DevBasis& B, const double* boxC, int nb,
                             int maxpt, const void* x, int ldx, int R, const void* khat, int Q, double kappa,
-                            double w2e, int conjx, int nsplit, int short_phase, void* S, hipStream_t st) {
+                            double w2e, int conjx, int nsplit, int phase_mode, void* S, hipStream_t st) {
   constexpr int NS = sizeof(TF) == 8 ? 5 : 4, NL = sizeof(TF) == 8 ? 9 : 6;
   if (R != 1 && R != 2 && R != 4) return hipErrorInvalidValue;
 #define AGG(RC_, NT_) agg_launch<TF, RC_, NT_>(G, I, B, boxC, nb, maxpt, x, ldx, khat, Q, kappa, w2e, conjx, nsplit, S, st)
-  if (short_phase) {
+  if (phase_mode == 1) {
     if (R == 1) AGG(1, NS); else if (R == 2) AGG(2, NS); else AGG(4, NS);
-  } else {
+  } else if (phase_mode == 2) {
     if (R == 1) AGG(1, NL); else if (R == 2) AGG(2, NL); else AGG(4, NL);
+  } else {
+    if (R == 1) AGG(1, 0); else if (R == 2) AGG(2, 0); else AGG(4, 0);
   }
 #undef AGG
   return hipGetLastError();
@@ -427,16 +432,18 @@ static void rec_launch(const DevGeo& G, const DevInc& I, const DevBasis& B, cons
 template <typename TF, typename TN>
 hipError_t launch_receive(const DevGeo& G, const DevInc& I, const DevBasis& B, const DevNear& NB,
                           const double* boxC, int nb, int maxpt, const void* Gin, const void* khat, int Q,
-                          double kappa, const void* part, int R, int flags, int short_phase, void* y, int ldy,
+                          double kappa, const void* part, int R, int flags, int phase_mode, void* y, int ldy,
                           hipStream_t st) {
   constexpr int NS = sizeof(TF) == 8 ? 5 : 4, NL = sizeof(TF) == 8 ? 9 : 6;
   if (R != 1 && R != 2 && R != 4) return hipErrorInvalidValue;
 #define REC(RC_, NT_) \
   rec_launch<TF, TN, RC_, NT_>(G, I, B, NB, boxC, nb, maxpt, Gin, khat, Q, kappa, part, flags, y, ldy, st)
-  if (short_phase) {
+  if (phase_mode == 1) {
     if (R == 1) REC(1, NS); else if (R == 2) REC(2, NS); else REC(4, NS);
-  } else {
+  } else if (phase_mode == 2) {
     if (R == 1) REC(1, NL); else if (R == 2) REC(2, NL); else REC(4, NL);
+  } else {
+    if (R == 1) REC(1, 0); else if (R == 2) REC(2, 0); else REC(4, 0);
   }
 #undef REC
   return hipGetLastError();

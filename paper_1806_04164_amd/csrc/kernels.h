@@ -23,7 +23,7 @@ size_t receive_smem(int maxpt, int Q, int R, int RC, int tf_bytes);
 template <typename TF>
 hipError_t launch_aggregate(const DevGeo& G, const DevInc& I, const DevBasis& B, const double* boxC, int nb,
                             int maxpt, const void* x, int ldx, int R, const void* khat, int Q, double kappa,
-                            double w2e, int conjx, int nsplit, int short_phase, void* S, hipStream_t st);
+                            double w2e, int conjx, int nsplit, int phase_mode, void* S, hipStream_t st);
 template <typename TF>
 hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* Sc, void* Sp, const void* Ft,
                            const void* ph, int Q, int R, void* Ywork, hipStream_t st);
@@ -33,7 +33,7 @@ hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, vo
 template <typename TF, typename TN>
 hipError_t launch_receive(const DevGeo& G, const DevInc& I, const DevBasis& B, const DevNear& NB,
                           const double* boxC, int nb, int maxpt, const void* Gin, const void* khat, int Q,
-                          double kappa, const void* part, int R, int flags, int short_phase, void* y, int ldy,
+                          double kappa, const void* part, int R, int flags, int phase_mode, void* y, int ldy,
                           hipStream_t st);
 template <typename TN>
 hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N, int R, int conjx, void* xb,

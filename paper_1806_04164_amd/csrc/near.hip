@@ -223,84 +223,79 @@ __global__ void k_diag(DevGeo G, DevBasis B, double* diag_abs, double k, double 
 }
 
 // ---------------------------------------------------------------------------
-// SpMM over the stored upper-triangle blocks.  One workgroup per block
-// (a, b): the row part r = Z_ab x_b goes to the partial slot of the rows, and
-// for a < b the transposed part c = Z_ab^T x_a (Z is symmetric) to the slot
-// of the columns.  The block is streamed through LDS in row panels with
-// coalesced loads; threads 0..127 form row sums (one row each), threads
-// 128..255 column sums (one column each, carried across panels).  Every sum
-// runs in a fixed order, without atomics: the result is bitwise reproducible.
+// SpMM over the stored upper-triangle blocks.  For block (a, b) the row part
+// r = Z_ab x_b goes to the partial slot of its rows and, for a < b, the
+// transposed part c = Z_ab^T x_a (Z is symmetric) to a column slot.  Work
+// unit = one row panel of one block (at most 16 KiB of entries), so large
+// blocks spread over several workgroups and every workgroup streams one
+// 16-byte-vectorised panel into LDS; threads 0..127 then form its row sums
+// (one row each) and threads 128..255 its column sums (one column each, into
+// the panel's own column slot).  The reception kernel adds the slots in a
+// fixed order: no atomics, bitwise reproducible.
 // ---------------------------------------------------------------------------
 template <typename TN, int RC>
 __global__ void __launch_bounds__(256) k_near_spmm(DevNear NB, const cx<TN>* __restrict__ Z,
                                                    const cx<TN>* __restrict__ xb, int ldx,
                                                    cx<TN>* __restrict__ part, int R) {
-  constexpr int MAXB = 128;  // max unknowns per box (checked on the host)
-  constexpr int ZCAP = sizeof(TN) == 4 ? 4096 : 2048;  // 32 KiB panel
-  __shared__ cx<TN> Zs[ZCAP];
-  __shared__ cx<TN> xa_s[MAXB * RC];
-  __shared__ cx<TN> xb_s[MAXB * RC];
-  const int blk = blockIdx.x;
+  constexpr int ZCAP = sizeof(TN) == 4 ? 2048 : 1024;   // 16 KiB panel: 8 workgroups per CU
+  constexpr int EPV = 16 / sizeof(cx<TN>);              // entries per 16-byte load
+  __shared__ __align__(16) cx<TN> Zs[ZCAP];
+  __shared__ cx<TN> xa_s[128 * RC];
+  __shared__ cx<TN> xb_s[128 * RC];
+  const int task = blockIdx.x;
+  const int blk = NB.t_blk[task], i0 = NB.t_i0[task], i1 = NB.t_i1[task];
   const int a = NB.blk_a[blk], b = NB.blk_b[blk];
-  const int u0 = NB.box_ptr[a], na = NB.box_ptr[a + 1] - u0;
+  const int u0 = NB.box_ptr[a];
   const int v0 = NB.box_ptr[b], nb = NB.box_ptr[b + 1] - v0;
   const bool offdiag = a != b;
-  for (int e = threadIdx.x; e < nb * R; e += blockDim.x) {
-    int j = e / R, r = e - j * R;
-    xb_s[j * RC + r] = xb[(size_t)(v0 + j) * ldx + r];
-  }
-  if (offdiag)
-    for (int e = threadIdx.x; e < na * R; e += blockDim.x) {
-      int i = e / R, r = e - i * R;
-      xa_s[i * RC + r] = xb[(size_t)(u0 + i) * ldx + r];
-    }
-  const cx<TN>* Zb = Z + NB.blk_off[blk];
-  cx<TN>* prow = part + (size_t)NB.prow[blk] * R;
   const int tid = threadIdx.x;
   const int jc = tid - 128;
-  cx<TN> cacc[RC];
-#pragma unroll
-  for (int r = 0; r < RC; ++r) cacc[r] = mk<TN>(0, 0);
-  int rpp = ZCAP / nb;
-  if (rpp > 128) rpp = 128;
-  for (int i0 = 0; i0 < na; i0 += rpp) {
-    const int i1 = i0 + rpp < na ? i0 + rpp : na;
-    const int cnt = (i1 - i0) * nb;
-    __syncthreads();
-    const cx<TN>* src = Zb + (size_t)i0 * nb;
-    for (int e = tid; e < cnt; e += blockDim.x) Zs[e] = src[e];
-    __syncthreads();
-    if (tid < 128) {
-      const int i = i0 + tid;
-      if (i < i1) {
-        cx<TN> racc[RC];
-#pragma unroll
-        for (int r = 0; r < RC; ++r) racc[r] = mk<TN>(0, 0);
-        const cx<TN>* zr = Zs + (size_t)(i - i0) * nb;
-        for (int j = 0; j < nb; ++j) {
-          const cx<TN> z = zr[j];
-#pragma unroll
-          for (int r = 0; r < RC; ++r)
-            if (r < R) cfma(racc[r], z, xb_s[j * RC + r]);
-        }
-#pragma unroll
-        for (int r = 0; r < RC; ++r)
-          if (r < R) prow[(size_t)i * R + r] = racc[r];
-      }
-    } else if (offdiag && jc < nb) {
-      for (int i = i0; i < i1; ++i) {
-        const cx<TN> z = Zs[(size_t)(i - i0) * nb + jc];
-#pragma unroll
-        for (int r = 0; r < RC; ++r)
-          if (r < R) cfma(cacc[r], z, xa_s[i * RC + r]);
-      }
-    }
+  const int nr = i1 - i0;
+  const int cnt = nr * nb;
+  const cx<TN>* src0 = Z + NB.blk_off[blk] + (size_t)i0 * nb;  // 16-byte aligned (host)
+  {
+    const float4* src = (const float4*)src0;
+    float4* dst = (float4*)Zs;
+    const int nv = cnt / EPV;
+    for (int e = tid; e < nv; e += blockDim.x) dst[e] = src[e];
+    if (EPV == 2 && (cnt & 1) && tid == 0) Zs[cnt - 1] = src0[cnt - 1];
   }
-  if (offdiag && tid >= 128 && jc < nb) {
-    cx<TN>* pcol = part + (size_t)NB.pcol[blk] * R;
+  if (tid < 128) {
+    if (tid < nb)
 #pragma unroll
-    for (int r = 0; r < RC; ++r)
-      if (r < R) pcol[(size_t)jc * R + r] = cacc[r];
+      for (int r = 0; r < RC; ++r) xb_s[tid * RC + r] = xb[(size_t)(v0 + tid) * ldx + r];
+  } else if (offdiag && jc < nr) {
+#pragma unroll
+    for (int r = 0; r < RC; ++r) xa_s[jc * RC + r] = xb[(size_t)(u0 + i0 + jc) * ldx + r];
+  }
+  __syncthreads();
+  if (tid < 128) {
+    if (tid < nr) {
+      cx<TN> racc[RC];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) racc[r] = mk<TN>(0, 0);
+      const cx<TN>* zr = Zs + (size_t)tid * nb;
+      for (int j = 0; j < nb; ++j) {
+        const cx<TN> z = zr[j];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) cfma(racc[r], z, xb_s[j * RC + r]);
+      }
+      cx<TN>* prow = part + ((size_t)NB.prow[blk] + i0 + tid) * R;
+#pragma unroll
+      for (int r = 0; r < RC; ++r) prow[r] = racc[r];
+    }
+  } else if (offdiag && jc < nb) {
+    cx<TN> cacc[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) cacc[r] = mk<TN>(0, 0);
+    for (int i = 0; i < nr; ++i) {
+      const cx<TN> z = Zs[(size_t)i * nb + jc];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) cfma(cacc[r], z, xa_s[i * RC + r]);
+    }
+    cx<TN>* pcol = part + ((size_t)NB.pcol[task] + jc) * R;
+#pragma unroll
+    for (int r = 0; r < RC; ++r) pcol[r] = cacc[r];
   }
 }
 
@@ -329,18 +324,20 @@ hipError_t launch_diag(const DevGeo& G, const DevBasis& B, double* diag_abs, dou
 }
 
 template <typename TN>
-hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part,
-                            int R, hipStream_t st) {
-  if (NB.nblk == 0) return hipSuccess;
-  if (R <= 1)
-    hipLaunchKernelGGL((k_near_spmm<TN, 1>), dim3(NB.nblk), dim3(256), 0, st, NB, (const cx<TN>*)Z,
+hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part, int R,
+                            hipStream_t st) {
+  if (NB.ntask == 0) return hipSuccess;
+  if (R == 1)
+    hipLaunchKernelGGL((k_near_spmm<TN, 1>), dim3(NB.ntask), dim3(256), 0, st, NB, (const cx<TN>*)Z,
                        (const cx<TN>*)xb, ldx, (cx<TN>*)part, R);
-  else if (R <= 2)
-    hipLaunchKernelGGL((k_near_spmm<TN, 2>), dim3(NB.nblk), dim3(256), 0, st, NB, (const cx<TN>*)Z,
+  else if (R == 2)
+    hipLaunchKernelGGL((k_near_spmm<TN, 2>), dim3(NB.ntask), dim3(256), 0, st, NB, (const cx<TN>*)Z,
+                       (const cx<TN>*)xb, ldx, (cx<TN>*)part, R);
+  else if (R == 4)
+    hipLaunchKernelGGL((k_near_spmm<TN, 4>), dim3(NB.ntask), dim3(256), 0, st, NB, (const cx<TN>*)Z,
                        (const cx<TN>*)xb, ldx, (cx<TN>*)part, R);
   else
-    hipLaunchKernelGGL((k_near_spmm<TN, 4>), dim3(NB.nblk), dim3(256), 0, st, NB, (const cx<TN>*)Z,
-                       (const cx<TN>*)xb, ldx, (cx<TN>*)part, R);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 template hipError_t launch_near_spmm<float>(const DevNear&, const void*, const void*, int, void*, int,

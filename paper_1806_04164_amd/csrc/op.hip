@@ -37,7 +37,7 @@ struct pie_op {
   int max_rhs = 1, rc = 1, L = 0, N = 0, ne = 0, nt = 0;
   int maxpt = 0;
   int nsplit = 1;  // aggregation point-loop split (fixed per operator: RHS-batch-independent order)
-  int short_phase = 0;  // 1: every pattern phase |kappa khat.(r - C)| is within the short Taylor bound
+  int phase_mode = 0;  // pattern phases: 1 short Taylor, 2 long Taylor, 0 library sincos
   double theta_max = 0.0;
   // device geometry
   double *dV = nullptr, *dP = nullptr, *dW = nullptr, *dC = nullptr, *dN = nullptr;
@@ -50,6 +50,7 @@ struct pie_op {
   // near field
   pie::DevNear NB{};
   void* dNear = nullptr;
+  int64_t ntask = 0;
   int64_t near_entries = 0, near_stored = 0, nslots = 0;
   // second stream for the near field, forked from and joined to the caller's
   hipStream_t side = nullptr;
@@ -267,7 +268,12 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     set_error("a finest box holds more than 128 unknowns; use more levels");
     return PIE_ERR_UNSUPPORTED;
   }
-  std::vector<int32_t> ba, bb, prow, pcol, row_ptr(nbL + 1, 0), col_ptr(nbL + 1, 0), col_blk;
+  // blocks (a <= b) grouped by row box; each block split into row panels of
+  // at most one LDS panel (2048 FP32 / 1024 FP64 entries, even row starts so
+  // panels stay 16-byte aligned), one SpMM workgroup per panel
+  const int zcap = op->near_prec == PIE_FP32 ? 2048 : 1024;
+  std::vector<int32_t> ba, bb, prow, row_ptr(nbL + 1, 0), col_ptr(nbL + 1, 0), col_blk;
+  std::vector<int32_t> tbk, ti0, ti1, tpc;
   std::vector<int64_t> boff;
   std::vector<std::vector<int32_t>> cols(nbL);
   int64_t off = 0, slot = 0, entries = 0;
@@ -280,16 +286,24 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
       ba.push_back(a);
       bb.push_back(b);
       boff.push_back(off);
-      off += ((int64_t)na * nb + 3) & ~int64_t(3);  // 4-entry aligned blocks
+      off += ((int64_t)na * nb + 3) & ~int64_t(3);  // 4-entry (32-byte FP32) aligned blocks
       entries += (int64_t)na * nb;
       prow.push_back((int32_t)slot);
       slot += na;
-      if (b != a) {
-        pcol.push_back((int32_t)slot);
-        slot += nb;
-        cols[b].push_back(id);
-      } else {
-        pcol.push_back(-1);
+      int rpp = std::min(128, zcap / nb);
+      if (op->near_prec == PIE_FP32 && (nb & 1) && rpp > 1) rpp &= ~1;
+      for (int i0 = 0; i0 < na; i0 += rpp) {
+        int tid_ = (int)tbk.size();
+        tbk.push_back(id);
+        ti0.push_back(i0);
+        ti1.push_back(std::min(na, i0 + rpp));
+        if (b != a) {
+          tpc.push_back((int32_t)slot);
+          slot += nb;
+          cols[b].push_back(tid_);
+        } else {
+          tpc.push_back(-1);
+        }
       }
     }
     row_ptr[a + 1] = (int32_t)ba.size();
@@ -301,13 +315,16 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   op->near_stored = off;
   op->near_entries = entries;
   op->nslots = slot;
-  int32_t *dba, *dbb, *dprow, *dpcol, *dbp, *drp, *dcp, *dcb;
+  op->ntask = (int64_t)tbk.size();
+  int32_t *dba, *dbb, *dprow, *dbp, *drp, *dcp, *dcb, *dtb, *dti0, *dti1, *dtpc;
   int64_t* dbo;
   if ((s = upload(op, &dba, ba)) || (s = upload(op, &dbb, bb)) || (s = upload(op, &dbo, boff)) ||
-      (s = upload(op, &dprow, prow)) || (s = upload(op, &dpcol, pcol)) || (s = upload(op, &dbp, box_ptr)) ||
-      (s = upload(op, &drp, row_ptr)) || (s = upload(op, &dcp, col_ptr)) || (s = upload(op, &dcb, col_blk)))
+      (s = upload(op, &dprow, prow)) || (s = upload(op, &dbp, box_ptr)) || (s = upload(op, &drp, row_ptr)) ||
+      (s = upload(op, &dcp, col_ptr)) || (s = upload(op, &dcb, col_blk)) || (s = upload(op, &dtb, tbk)) ||
+      (s = upload(op, &dti0, ti0)) || (s = upload(op, &dti1, ti1)) || (s = upload(op, &dtpc, tpc)))
     return s;
-  op->NB = DevNear{(int32_t)ba.size(), dba, dbb, dbo, dprow, dpcol, dbp, drp, dcp, dcb};
+  op->NB = DevNear{(int32_t)ba.size(), dba, dbb, dbo, dprow, (int32_t)tbk.size(), dtb, dti0, dti1, dtpc,
+                   dbp, drp, dcp, dcb};
   // ---------------- incidences
   std::vector<int32_t> iptr(nbL + 1, 0), itri, irwg, ifv, ipulse, uslot(2 * (size_t)N, -1);
   std::vector<double> irs, ird;
@@ -415,7 +432,8 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
         }
     }
     op->theta_max = op->kappa_l[L] * rmax * (1.0 + 1e-12);
-    op->short_phase = op->theta_max <= (op->far_prec == PIE_FP32 ? 0.2 : 0.1) ? 1 : 0;
+    const double lim = op->far_prec == PIE_FP32 ? 0.2 : 0.1;
+    op->phase_mode = op->theta_max <= lim ? 1 : (op->theta_max <= 0.5 ? 2 : 0);
   }
   // ---------------- k-space samples and tables (FP64)
   const int Q = op->Q, tau = op->tau;
@@ -634,7 +652,7 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
   if (far) {
     if ((e = stage(op, PIE_STAGE_AGGREGATE, st, [&] {
            return launch_aggregate<TF>(G, op->I, B, op->lv[L].centre, op->lv[L].nb, op->maxpt, x, ld, R,
-                                       op->dKhat, Q, op->kappa_l[L], op->w2e, adj, op->nsplit, op->short_phase, op->dS[L], st);
+                                       op->dKhat, Q, op->kappa_l[L], op->w2e, adj, op->nsplit, op->phase_mode, op->dS[L], st);
          })) != hipSuccess)
       return hip_fail(e, "aggregate");
     for (int l = L - 1; l >= 3; --l)
@@ -658,7 +676,7 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
   if ((e = stage(op, PIE_STAGE_RECEIVE, st, [&] {
          return launch_receive<TF, TN>(G, op->I, B, op->NB, op->lv[L].centre, op->lv[L].nb, op->maxpt,
                                        op->dG[L], op->dKhat, Q, op->kappa_l[L], op->dPart, R, rflags,
-                                       op->short_phase, y, ld, st);
+                                       op->phase_mode, y, ld, st);
        })) != hipSuccess)
     return hip_fail(e, "receive");
   return PIE_OK;

@@ -255,6 +255,13 @@ pie_status pie_farfield(pie_op* op, const void* x, int64_t R,
                         const double* dirs, int64_t nd, void* F,
                         void* stream);
 
+/* Adjoint of pie_farfield (for gradients of far-field quantities):
+ * gx = Phi^H gF with F = Phi x as defined above.  gF: device complex128
+ * [R][nd][3]; gx: device complex128 [N][R] (pulse rows set to zero). */
+pie_status pie_farfield_adjoint(pie_op* op, const void* gF, int64_t R,
+                                const double* dirs, int64_t nd, void* gx,
+                                void* stream);
+
 #ifdef __cplusplus
 }
 #endif

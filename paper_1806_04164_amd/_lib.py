@@ -40,7 +40,7 @@ EXPORTS = [
     "pie_options_default", "pie_operator_create", "pie_operator_destroy", "pie_operator_info",
     "pie_operator_level", "pie_matvec", "pie_matvec_near", "pie_matvec_far",
     "pie_rhs_planewave", "pie_solve_opts_default", "pie_solve", "pie_farfield",
-    "pie_profile_enable", "pie_profile_read",
+    "pie_profile_enable", "pie_profile_read", "pie_farfield_adjoint",
 ]
 STAGES = ["permute", "near", "aggregate", "shift_up", "translate", "receive"]
 
@@ -101,6 +101,7 @@ def lib():
         "pie_farfield": (I32, [P, P, I64, P, I64, P, P]),
         "pie_profile_enable": (I32, [P, I32]),
         "pie_profile_read": (I32, [P, P, P]),
+        "pie_farfield_adjoint": (I32, [P, P, I64, P, I64, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -131,6 +131,61 @@ hipError_t launch_farfield(const DevGeo& G, const double* s, const int32_t* tri,
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of the far-field map: for F = Phi x as above,
+//   gx[n][r] = sum_d conj(Phi[d][:, n]) . gF[r][d][:]
+//            = sum_d conj(i w mu0/4pi) conj(Jn(d)) . ((I - rhat rhat) gF[r][d]),
+//   Jn(d) = int f_n exp(-i k rhat_d.r') dr'.
+// One thread per (RWG function, RHS); pulse rows of gx are zero.
+// ---------------------------------------------------------------------------
+__global__ void k_farfield_adj(DevGeo G, const double* __restrict__ s, const int32_t* __restrict__ tri,
+                               const int32_t* __restrict__ fv, int ne, int nt, const cx<double>* __restrict__ gF,
+                               int R, const double* __restrict__ dirs, int nd, double k, double omega,
+                               cx<double>* __restrict__ gx) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)(ne + nt) * R) return;
+  const int n = (int)(e / R), r = (int)(e - (int64_t)n * R);
+  if (n >= ne) {
+    gx[e] = mk(0.0, 0.0);
+    return;
+  }
+  const double f = omega * 4.0e-7 * 3.14159265358979323846 / (4.0 * 3.14159265358979323846);
+  cx<double> acc = mk(0.0, 0.0);
+  for (int dd = 0; dd < nd; ++dd) {
+    const double* rh = dirs + 3 * dd;
+    const cx<double>* g = gF + ((size_t)r * nd + dd) * 3;
+    cx<double> gr = (rh[0] * g[0] + rh[1] * g[1]) + rh[2] * g[2];
+    cx<double> gt[3];
+    for (int c = 0; c < 3; ++c) gt[c] = g[c] - rh[c] * gr;
+    // conj(Jn) . gt, Jn = sum W s (P - p) exp(-i k rhat.P)  -> conj(exp) = exp(+i k rhat.P)
+    cx<double> sum = mk(0.0, 0.0);
+    for (int h = 0; h < 2; ++h) {
+      const int t = tri[2 * n + h];
+      const double* pv = G.V + 3 * fv[2 * n + h];
+      const double sc = s[2 * n + h];
+      for (int i = 0; i < 7; ++i) {
+        const double* P = G.P + 21 * t + 3 * i;
+        double sn, cs;
+        sincos(k * (rh[0] * P[0] + rh[1] * P[1] + rh[2] * P[2]), &sn, &cs);
+        cx<double> dot = ((P[0] - pv[0]) * gt[0] + (P[1] - pv[1]) * gt[1]) + (P[2] - pv[2]) * gt[2];
+        sum = sum + (G.W[7 * t + i] * sc) * (mk(cs, sn) * dot);
+      }
+    }
+    acc = acc + sum;
+  }
+  // times conj(i f) = -i f
+  gx[e] = mk(f * acc.im, -f * acc.re);
+}
+
+hipError_t launch_farfield_adj(const DevGeo& G, const double* s, const int32_t* tri, const int32_t* fv, int ne,
+                               int nt, const void* gF, int R, const double* dirs, int nd, double k, double omega,
+                               void* gx, hipStream_t st) {
+  int64_t n = (int64_t)(ne + nt) * R;
+  hipLaunchKernelGGL(k_farfield_adj, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, G, s, tri, fv, ne, nt,
+                     (const cx<double>*)gF, R, dirs, nd, k, omega, (cx<double>*)gx);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Solver vector kernels on [N][R] complex128 blocks.
 // ---------------------------------------------------------------------------
 __global__ void k_scale_rows(const cx<double>* __restrict__ x, const double* __restrict__ d, int N, int R,

@@ -46,6 +46,9 @@ hipError_t launch_rhs(const DevGeo& G, const double* basis_canon_s, const int32_
 hipError_t launch_farfield(const DevGeo& G, const double* s_canon, const int32_t* tri_canon,
                            const int32_t* fv_canon, int ne, const void* x, int R, const double* dirs, int nd,
                            double k, double omega, void* F, hipStream_t st);
+hipError_t launch_farfield_adj(const DevGeo& G, const double* s_canon, const int32_t* tri_canon,
+                               const int32_t* fv_canon, int ne, int nt, const void* gF, int R, const double* dirs,
+                               int nd, double k, double omega, void* gx, hipStream_t st);
 // y[:, r] = alpha_r-free helpers for the solver (complex128, [N][R]).
 hipError_t launch_scale_rows(const void* x, const double* d, int N, int R, void* y, hipStream_t st);
 hipError_t launch_dots(const void* V, int64_t vstride, int nv, const void* w, int N, int R, void* out,

@@ -1063,6 +1063,30 @@ pie_status pie_farfield(pie_op* op, const void* x, int64_t R, const double* dirs
   return PIE_OK;
 }
 
+pie_status pie_farfield_adjoint(pie_op* op, const void* gF, int64_t R, const double* dirs, int64_t nd, void* gx,
+                                void* stream) {
+  if (!op || !gF || !dirs || !gx || nd < 1) {
+    pie::set_error("null argument or no directions");
+    return PIE_ERR_ARG;
+  }
+  if (R < 1 || R > op->max_rhs) {
+    pie::set_error("R must be in [1, max_rhs]");
+    return PIE_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (nd > op->ndirs_cap) {
+    pie_status s = dalloc(op, &op->dDirs, 3 * (size_t)nd);
+    if (s) return s;
+    op->ndirs_cap = nd;
+  }
+  HIPCHK(hipMemcpyAsync(op->dDirs, dirs, 3 * nd * sizeof(double), hipMemcpyHostToDevice, st), "dirs copy");
+  hipError_t e = pie::launch_farfield_adj(geo(op), op->dCs, op->dCtri, op->dCfv, op->ne, op->nt, gF, (int)R,
+                                          op->dDirs, (int)nd, op->k, op->omega, gx, st);
+  if (e != hipSuccess) return hip_fail(e, "farfield adjoint");
+  HIPCHK(hipStreamSynchronize(st), "farfield adjoint");
+  return PIE_OK;
+}
+
 void pie_solve_opts_default(pie_solve_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));

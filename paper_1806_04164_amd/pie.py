@@ -207,3 +207,14 @@ class Operator:
         check(lib().pie_farfield(self.h, _dev(x, self.N), R, _ptr(dirs), dirs.shape[0],
                                  ctypes.c_void_p(F.data_ptr()), _stream(stream)))
         return F
+
+    def farfield_adjoint(self, gF, dirs, stream=None):
+        import torch
+        if not (gF.is_cuda and gF.dtype == torch.complex128 and gF.is_contiguous() and gF.dim() == 3):
+            raise TypeError("gF must be a contiguous complex128 [R, nd, 3] GPU tensor")
+        R = gF.shape[0]
+        dirs = np.ascontiguousarray(np.atleast_2d(dirs), np.float64)
+        gx = torch.empty((self.N, R), dtype=torch.complex128, device="cuda")
+        check(lib().pie_farfield_adjoint(self.h, ctypes.c_void_p(gF.data_ptr()), R, _ptr(dirs), dirs.shape[0],
+                                         ctypes.c_void_p(gx.data_ptr()), _stream(stream)))
+        return gx

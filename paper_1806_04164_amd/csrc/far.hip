@@ -128,6 +128,7 @@ __global__ void __launch_bounds__(128) k_child_filter(DevLevel Lc, const cx<TF>*
     cx<TF> s[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) s[k] = mk<TF>(0, 0);
+#pragma unroll 4
     for (int qq = 0; qq < Q; ++qq) {
       const TF f = Ft[(size_t)qq * Q + q];
       const cx<TF>* v = Ss + (size_t)qq * ncol + r;
@@ -191,6 +192,7 @@ __global__ void __launch_bounds__(256) k_translate(DevLevel Lv, const cx<TF>* __
     cx<TF> acc[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) acc[k] = mk<TF>(0, 0);
+#pragma unroll 4
     for (int it = i0; it < i1; ++it) {
       const int src = Lv.il_src[it], off = Lv.il_off[it];
       const cx<TF> t = T[(size_t)off * Q + q];
@@ -199,6 +201,7 @@ __global__ void __launch_bounds__(256) k_translate(DevLevel Lv, const cx<TF>* __
       for (int k = 0; k < 5; ++k) cfma(acc[k], t, sv[k * R]);
     }
     if (has_parent) {
+#pragma unroll 4
       for (int qq = 0; qq < Q; ++qq) {
         const TF f = Fp[(size_t)qq * Q + q];
         const cx<TF>* h = H + (size_t)qq * ncol + r;

@@ -54,16 +54,16 @@ def build_ops(w, modes, max_rhs):
     return mesh, tree, ops
 
 
-def time_mvm(op, x, y, steps, warmup, profile):
+def time_mvm(op, x, y, steps, warmup):
+    """Timed MVMs without instrumentation (HIP events on the caller's stream
+    around the whole loop), then the same number with per-stage events for
+    the stage breakdown."""
     import torch
     for _ in range(warmup):
         op.matvec(x, y)
     torch.cuda.synchronize()
-    if profile:
-        op.profile(True)
     s0 = torch.cuda.Event(enable_timing=True)
     s1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     s0.record()
     for _ in range(steps):
@@ -71,10 +71,14 @@ def time_mvm(op, x, y, steps, warmup, profile):
     s1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    stages = op.profile_read() if profile else None
-    if profile:
-        op.profile(False)
-    return s0.elapsed_time(s1) / steps, wall / steps, stages
+    ms = s0.elapsed_time(s1) / steps
+    op.profile(True)
+    for _ in range(steps):
+        op.matvec(x, y)
+    torch.cuda.synchronize()
+    stages = op.profile_read()
+    op.profile(False)
+    return ms, wall / steps, stages
 
 
 def time_near_only(op, x, y, steps):
@@ -147,7 +151,7 @@ def main():
     res = {}
     for m in modes:
         y = torch.empty_like(x)
-        ms, wall, stages = time_mvm(ops[m], x, y, args.steps, args.warmup, profile=True)
+        ms, wall, stages = time_mvm(ops[m], x, y, args.steps, args.warmup)
         res[m] = dict(ms=ms, wall_ms=wall * 1e3, stages=stages,
                       near_alone_ms=time_near_only(ops[m], x, y, args.steps))
         log(f"[bench] {m}: {ms:.4f} ms/MVM  stages(ms/launch) " +

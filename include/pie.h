@@ -199,9 +199,10 @@ pie_status pie_matvec_far(pie_op* op, const void* x, void* y, int64_t R,
 #define PIE_STAGE_NEAR 1      /* near-field SpMM                           */
 #define PIE_STAGE_AGGREGATE 2 /* finest-level radiation patterns           */
 #define PIE_STAGE_SHIFT_UP 3  /* child -> parent shifts                    */
-#define PIE_STAGE_TRANSLATE 4 /* translation (+ parent -> child shift)     */
+#define PIE_STAGE_TRANSLATE 4 /* interaction-list translations              */
 #define PIE_STAGE_RECEIVE 5   /* reception + near join + output permutation */
-#define PIE_NSTAGES 6
+#define PIE_STAGE_SHIFT_DOWN 6 /* parent -> child shifts                   */
+#define PIE_NSTAGES 7
 pie_status pie_profile_enable(pie_op* op, int32_t on);
 pie_status pie_profile_read(pie_op* op, double* ms, int64_t* launches);
 

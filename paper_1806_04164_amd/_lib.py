@@ -42,7 +42,7 @@ EXPORTS = [
     "pie_rhs_planewave", "pie_solve_opts_default", "pie_solve", "pie_farfield",
     "pie_profile_enable", "pie_profile_read", "pie_farfield_adjoint",
 ]
-STAGES = ["permute", "near", "aggregate", "shift_up", "translate", "receive"]
+STAGES = ["permute", "near", "aggregate", "shift_up", "translate", "receive", "shift_down"]
 
 
 class pie_options(ctypes.Structure):

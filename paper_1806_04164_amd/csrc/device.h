@@ -175,19 +175,35 @@ struct DevLevel {
   const int32_t* il_ptr;    // [nb+1]
   const int32_t* il_src;
   const int32_t* il_off;
+  int32_t nug;              // parent groups of the upward shift into this level
+  const int32_t* ug_ptr;    // [nug+1] parent ranges; each group has <= SHIFT_GROUP children
 };
+
+// Inter-level shift tiling: sample rows per thread, boxes per workgroup.
+constexpr int SQT = 8;
+constexpr int SHIFT_GROUP = 12;
+// Longest interaction list with a one-box buffer: 6^3 - 3^3 offsets.
+constexpr int IL_MAX = 189;
+// Translation offsets (max-norm 2 or 3 in box units).
+constexpr int TRANSLATE_OFFSETS = 316;
 
 // (finest box, triangle) incidences: up to three RWG functions of the box
 // that live on the triangle, and the triangle's pulse if it is in the box.
+// Geometry is stored relative to the box centre C, so that a thread forms a
+// quadrature point's source density or testing integral from independent
+// loads only.
 struct DevInc {
-  const int32_t* ptr;   // [nbL+1]
-  const int32_t* tri;   // [ninc]
-  const int32_t* rwg;   // [ninc][3] box-order slot or -1
-  const double* rs;     // [ninc][3] +-l/(2A)
-  const double* rd;     // [ninc][3] +-l/A
-  const int32_t* rfv;   // [ninc][3] free vertex
-  const int32_t* pulse; // [ninc] box-order slot or -1
-  const int32_t* uslot; // [N][2] incidence*4 + k for each unknown (k = 3: pulse)
+  const int32_t* ptr;   // [nbL+1] incidence range of each finest box
+  const double* pw;     // [ninc][7][4] (r_i - C, quadrature weight W_i)
+  const int32_t* xc;    // [ninc][4] canonical unknown of RWG slot k < 3 / of the pulse (k = 3), or -1
+  const double* rs;     // [ninc][3] +-l/(2A)  (0 for an empty slot)
+  const double* rd;     // [ninc][3] +-l/A     (0 for an empty slot)
+  const double* pv;     // [ninc][3][3] free vertex - C (0 for an empty slot)
+  // per box-order unknown u and half h (a pulse uses h = 0 only)
+  const int32_t* uj;    // [N][2] incidence index
+  const double* us;     // [N][2] +-l/(2A)
+  const double* ud;     // [N][2] +-l/A
+  const double* upv;    // [N][2][3] free vertex - C
 };
 
 }  // namespace pie

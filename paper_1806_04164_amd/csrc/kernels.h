@@ -19,22 +19,27 @@ hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, in
 
 // far.hip
 size_t aggregate_smem(int maxpt, int Q, int nsplit, int RC, int tf_bytes);
-size_t receive_smem(int maxpt, int Q, int R, int RC, int tf_bytes);
+size_t receive_smem(int maxpt, int Q, int maxjoin, int RC, int tf_bytes);
 template <typename TF>
-hipError_t launch_aggregate(const DevGeo& G, const DevInc& I, const DevBasis& B, const double* boxC, int nb,
-                            int maxpt, const void* x, int ldx, int R, const void* khat, int Q, double kappa,
-                            double w2e, int conjx, int nsplit, int phase_mode, void* S, hipStream_t st);
+hipError_t launch_aggregate(const DevInc& I, int nb, int maxpt, const void* x, int ldx, int R, const void* khat,
+                            int Q, double kappa, double w2e, int conjx, int nsplit, int phase_mode, void* S,
+                            hipStream_t st);
+// Filter tables (Ft for the upward, F for the downward shift) carry SQT
+// trailing zeros.
 template <typename TF>
 hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* Sc, void* Sp, const void* Ft,
-                           const void* ph, int Q, int R, void* Ywork, hipStream_t st);
+                           const void* ph, int Q, int R, hipStream_t st);
 template <typename TF>
-hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, void* Gout, int has_parent,
-                            const void* Gp, const void* Fp, const void* php, int Q, int R, hipStream_t st);
+hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const void* F, const void* ph, int Q,
+                             int R, hipStream_t st);
+// T: translation values [TRANSLATE_OFFSETS][Q].
+template <typename TF>
+hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, void* Gout, int Q, int R,
+                            hipStream_t st);
 template <typename TF, typename TN>
-hipError_t launch_receive(const DevGeo& G, const DevInc& I, const DevBasis& B, const DevNear& NB,
-                          const double* boxC, int nb, int maxpt, const void* Gin, const void* khat, int Q,
-                          double kappa, const void* part, int R, int flags, int phase_mode, void* y, int ldy,
-                          hipStream_t st);
+hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxpt, int maxjoin,
+                          const void* Gin, const void* khat, int Q, double kappa, const void* part, int R,
+                          int flags, int phase_mode, void* y, int ldy, hipStream_t st);
 template <typename TN>
 hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N, int R, int conjx, void* xb,
                              hipStream_t st);

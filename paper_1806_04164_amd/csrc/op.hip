@@ -36,6 +36,7 @@ struct pie_op {
   double xs = 0;
   int max_rhs = 1, rc = 1, L = 0, N = 0, ne = 0, nt = 0;
   int maxpt = 0;
+  int maxjoin = 0;  // longest near-field join list of a finest box
   int nsplit = 1;  // aggregation point-loop split (fixed per operator: RHS-batch-independent order)
   int phase_mode = 0;  // pattern phases: 1 short Taylor, 2 long Taylor, 0 library sincos
   double theta_max = 0.0;
@@ -55,6 +56,10 @@ struct pie_op {
   // second stream for the near field, forked from and joined to the caller's
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // third stream: the finest level's interaction-list translation, which
+  // needs only the finest patterns and overlaps the upward shifts
+  hipStream_t side2 = nullptr;
+  hipEvent_t ev_agg = nullptr, ev_il = nullptr;
   // incidences
   pie::DevInc I{};
   int64_t ninc = 0;
@@ -67,7 +72,6 @@ struct pie_op {
   std::vector<void*> dTl, dFl, dFtl, dPhl;
   // workspace
   std::vector<void*> dS, dG;
-  void* dY = nullptr;  // per-child filtered patterns of the shift-up (finest-level sized)
   void* dPart = nullptr;
   void* dXb = nullptr;
   double* dDiagScale = nullptr;  // |Z_uu|^-1/2, canonical order
@@ -81,8 +85,11 @@ struct pie_op {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
   ~pie_op() {
     if (side) (void)hipStreamDestroy(side);
+    if (side2) (void)hipStreamDestroy(side2);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_agg) (void)hipEventDestroy(ev_agg);
+    if (ev_il) (void)hipEventDestroy(ev_il);
     for (auto& u : ev_used) {
       (void)hipEventDestroy(u.second.first);
       (void)hipEventDestroy(u.second.second);
@@ -172,16 +179,20 @@ pie_status upload_tables(pie_op* op, const std::vector<double>& khat, const std:
   op->dFl.assign(op->L + 1, nullptr);
   op->dFtl.assign(op->L + 1, nullptr);
   op->dPhl.assign(op->L + 1, nullptr);
+  static_assert(TRANSLATE_OFFSETS == kNumOffsets, "offset table size");
   for (int l = 3; l <= op->L; ++l) {
     TF* t = nullptr;
     if ((s = upload(op, &t, cast_vec<TF>(T[l])))) return s;
     op->dTl[l] = t;
     if (l < op->L) {
-      TF* f = nullptr;
-      if ((s = upload(op, &f, cast_vec<TF>(F[l])))) return s;
-      op->dFl[l] = f;
+      // both layouts padded with SQT zeros (row tiles of the shift kernels)
       const int Q = op->Q;
-      std::vector<double> Ftr((size_t)Q * Q);
+      std::vector<double> Fp(F[l]);
+      Fp.resize((size_t)Q * Q + SQT, 0.0);
+      TF* f = nullptr;
+      if ((s = upload(op, &f, cast_vec<TF>(Fp)))) return s;
+      op->dFl[l] = f;
+      std::vector<double> Ftr((size_t)Q * Q + SQT, 0.0);
       for (int a = 0; a < Q; ++a)
         for (int b = 0; b < Q; ++b) Ftr[(size_t)b * Q + a] = F[l][(size_t)a * Q + b];
       TF* ft = nullptr;
@@ -369,13 +380,60 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   }
   op->ninc = (int64_t)itri.size();
   op->maxpt = 7 * maxinc;
-  int32_t *dip, *dit, *dir, *dif, *dipu, *dus;
-  double *dirs, *dird;
-  if ((s = upload(op, &dip, iptr)) || (s = upload(op, &dit, itri)) || (s = upload(op, &dir, irwg)) ||
-      (s = upload(op, &dirs, irs)) || (s = upload(op, &dird, ird)) || (s = upload(op, &dif, ifv)) ||
-      (s = upload(op, &dipu, ipulse)) || (s = upload(op, &dus, uslot)))
-    return s;
-  op->I = DevInc{dip, dit, dir, dirs, dird, dif, dipu, dus};
+  {
+    // geometry relative to the finest box centre (the same centre formula
+    // as the level tables below)
+    const Level& LL = t.lev[L];
+    const double dL = t.side / (double)(int64_t(1) << (L - 1));
+    auto centre = [&](int b, int c) { return t.origin[c] + ((double)LL.coords[3 * b + c] + 0.5) * dL; };
+    const size_t ni = itri.size();
+    std::vector<double> ipw(28 * ni), ipv(9 * ni, 0.0);
+    std::vector<int32_t> ixc(4 * ni, -1);
+    std::vector<int32_t> uj(2 * (size_t)N, 0);
+    std::vector<double> us(2 * (size_t)N, 0.0), ud(2 * (size_t)N, 0.0), upv(6 * (size_t)N, 0.0);
+    for (int b = 0; b < nbL; ++b) {
+      const double C[3] = {centre(b, 0), centre(b, 1), centre(b, 2)};
+      for (int j = iptr[b]; j < iptr[b + 1]; ++j) {
+        const int tr = itri[j];
+        for (int i = 0; i < 7; ++i) {
+          for (int c = 0; c < 3; ++c) ipw[28 * (size_t)j + 4 * i + c] = P[21 * (size_t)tr + 3 * i + c] - C[c];
+          ipw[28 * (size_t)j + 4 * i + 3] = W[7 * (size_t)tr + i];
+        }
+        for (int k = 0; k < 3; ++k) {
+          const int u = irwg[3 * j + k];
+          if (u < 0) {
+            irs[3 * j + k] = ird[3 * j + k] = 0.0;
+            continue;
+          }
+          ixc[4 * (size_t)j + k] = perm[u];
+          for (int c = 0; c < 3; ++c) ipv[9 * (size_t)j + 3 * k + c] = m.V[3 * (size_t)ifv[3 * j + k] + c] - C[c];
+        }
+        if (ipulse[j] >= 0) ixc[4 * (size_t)j + 3] = perm[ipulse[j]];
+      }
+      for (int u = box_ptr[b]; u < box_ptr[b + 1]; ++u)
+        for (int h = 0; h < 2; ++h) {
+          const int slot = uslot[2 * u + h];
+          const int j = slot >> 2, k = slot & 3;
+          uj[2 * u + h] = j;
+          if (k == 3) continue;
+          us[2 * u + h] = irs[3 * j + k];
+          ud[2 * u + h] = ird[3 * j + k];
+          for (int c = 0; c < 3; ++c) upv[6 * (size_t)u + 3 * h + c] = m.V[3 * (size_t)ifv[3 * j + k] + c] - C[c];
+        }
+    }
+    int32_t *dip, *dxc, *duj;
+    double *dpw, *drs, *drd, *dpv, *dus, *dud, *dupv;
+    if ((s = upload(op, &dip, iptr)) || (s = upload(op, &dpw, ipw)) || (s = upload(op, &dxc, ixc)) ||
+        (s = upload(op, &drs, irs)) || (s = upload(op, &drd, ird)) || (s = upload(op, &dpv, ipv)) ||
+        (s = upload(op, &duj, uj)) || (s = upload(op, &dus, us)) || (s = upload(op, &dud, ud)) ||
+        (s = upload(op, &dupv, upv)))
+      return s;
+    op->I = DevInc{dip, dpw, dxc, drs, drd, dpv, duj, dus, dud, dupv};
+  }
+  // longest near-field join list of a finest box (partial-sum slots staged in LDS by the reception)
+  op->maxjoin = 0;
+  for (int b = 0; b < nbL; ++b)
+    op->maxjoin = std::max(op->maxjoin, (row_ptr[b + 1] - row_ptr[b]) + (col_ptr[b + 1] - col_ptr[b]));
   // ---------------- levels
   op->lv.assign(L + 1, DevLevel{});
   op->s_l.assign(L + 1, 0.0);
@@ -385,6 +443,11 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   for (int l = 3; l <= L; ++l) {
     const Level& lvh = t.lev[l];
     const int nb = (int)lvh.nb;
+    for (int b = 0; b < nb; ++b)
+      if (lvh.il_ptr[b + 1] - lvh.il_ptr[b] > IL_MAX) {
+        set_error("interaction list longer than the one-box-buffer bound");
+        return PIE_ERR_MESH;
+      }
     const double d = t.side / (double)(int64_t(1) << (l - 1));
     op->d_l[l] = d;
     op->s_l[l] = std::min(1.0, op->k * d / op->xs);
@@ -406,6 +469,25 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
         (s = upload(op, &dilo, narrow32<int32_t>(lvh.il_off))))
       return s;
     if (l < L && (s = upload(op, &dchild, narrow32<int32_t>(lvh.child_ptr)))) return s;
+    // parent groups of the upward shift: runs of parents with at most
+    // SHIFT_GROUP children in total
+    int32_t* dug = nullptr;
+    int32_t nug = 0;
+    if (l < L) {
+      std::vector<int32_t> ug{0};
+      int64_t cnt = 0;
+      for (int p = 0; p < nb; ++p) {
+        const int64_t nc = lvh.child_ptr[p + 1] - lvh.child_ptr[p];
+        if (cnt + nc > SHIFT_GROUP) {
+          ug.push_back(p);
+          cnt = 0;
+        }
+        cnt += nc;
+      }
+      ug.push_back(nb);
+      nug = (int32_t)ug.size() - 1;
+      if ((s = upload(op, &dug, ug))) return s;
+    }
     dl.centre = dcen;
     dl.parent = dpar;
     dl.octant = doct;
@@ -413,6 +495,8 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     dl.il_ptr = dilp;
     dl.il_src = dils;
     dl.il_off = dilo;
+    dl.nug = nug;
+    dl.ug_ptr = dug;
     op->lv[l] = dl;
     op->il_pairs += (int64_t)lvh.il_src.size();
   }
@@ -536,9 +620,8 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   for (int rc : {4, 2, 1}) {
     if (rc > op->max_rhs && rc > 1) continue;
     size_t a = aggregate_smem(op->maxpt, Q, 1, rc, tfb);
-    size_t r = receive_smem(op->maxpt, Q, rc, rc, tfb);
-    size_t sh = (size_t)2 * Q * 5 * rc * 2 * tfb;
-    if (a <= 65536 && r <= 65536 && sh <= 65536) {
+    size_t r = receive_smem(op->maxpt, Q, op->maxjoin, rc, tfb);
+    if (a <= 65536 && r <= 65536) {
       op->rc = rc;
       break;
     }
@@ -562,11 +645,6 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     if ((s = dalloc(op, &a, n)) || (s = dalloc(op, &b, n))) return s;
     op->dS[l] = a;
     op->dG[l] = b;
-  }
-  {
-    unsigned char* yw;
-    if ((s = dalloc(op, &yw, (size_t)op->lv[L].nb * Q * 5 * op->rc * cxf))) return s;
-    op->dY = yw;
   }
   unsigned char *part, *xb;
   if ((s = dalloc(op, &part, (size_t)op->nslots * op->rc * cxn)) || (s = dalloc(op, &xb, (size_t)N * op->rc * cxn)))
@@ -647,36 +725,51 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
       return hip_fail(e, "near spmm");
   }
   if (fork) HIPCHK(hipEventRecord(op->ev_join, sn), "join");
-  const DevGeo G = geo(op);
   const DevBasis B = basis(op);
   if (far) {
     if ((e = stage(op, PIE_STAGE_AGGREGATE, st, [&] {
-           return launch_aggregate<TF>(G, op->I, B, op->lv[L].centre, op->lv[L].nb, op->maxpt, x, ld, R,
-                                       op->dKhat, Q, op->kappa_l[L], op->w2e, adj, op->nsplit, op->phase_mode, op->dS[L], st);
+           return launch_aggregate<TF>(op->I, op->lv[L].nb, op->maxpt, x, ld, R, op->dKhat, Q, op->kappa_l[L],
+                                       op->w2e, adj, op->nsplit, op->phase_mode, op->dS[L], st);
          })) != hipSuccess)
       return hip_fail(e, "aggregate");
+    // finest-level translation on the third stream, concurrent with the
+    // upward shifts and the coarser translations
+    const bool fork2 = L > 3;
+    auto translate = [&](int l, hipStream_t s) {
+      return stage(op, PIE_STAGE_TRANSLATE, s, [&] {
+        return launch_translate<TF>(op->lv[l], op->dS[l], op->dTl[l], op->dG[l], Q, R, s);
+      });
+    };
+    if (fork2) {
+      HIPCHK(hipEventRecord(op->ev_agg, st), "fork");
+      HIPCHK(hipStreamWaitEvent(op->side2, op->ev_agg, 0), "fork");
+      if ((e = translate(L, op->side2)) != hipSuccess) return hip_fail(e, "translate");
+      HIPCHK(hipEventRecord(op->ev_il, op->side2), "join");
+    }
     for (int l = L - 1; l >= 3; --l)
       if ((e = stage(op, PIE_STAGE_SHIFT_UP, st, [&] {
              return launch_shift_up<TF>(op->lv[l], op->lv[l + 1], op->dS[l + 1], op->dS[l], op->dFtl[l],
-                                        op->dPhl[l], Q, R, op->dY, st);
+                                        op->dPhl[l], Q, R, st);
            })) != hipSuccess)
         return hip_fail(e, "shift up");
-    for (int l = 3; l <= L; ++l) {
-      const bool hp = l > 3;
-      if ((e = stage(op, PIE_STAGE_TRANSLATE, st, [&] {
-             return launch_translate<TF>(op->lv[l], op->dS[l], op->dTl[l], op->dG[l], hp,
-                                         hp ? op->dG[l - 1] : nullptr, hp ? op->dFl[l - 1] : nullptr,
-                                         hp ? op->dPhl[l - 1] : nullptr, Q, R, st);
+    for (int l = 3; l <= L; ++l)
+      if (l < L || !fork2)
+        if ((e = translate(l, st)) != hipSuccess) return hip_fail(e, "translate");
+    for (int l = 4; l <= L; ++l) {
+      if (l == L && fork2) HIPCHK(hipStreamWaitEvent(st, op->ev_il, 0), "join");
+      if ((e = stage(op, PIE_STAGE_SHIFT_DOWN, st, [&] {
+             return launch_shift_down<TF>(op->lv[l], op->dG[l - 1], op->dG[l], op->dFl[l - 1], op->dPhl[l - 1],
+                                          Q, R, st);
            })) != hipSuccess)
-        return hip_fail(e, "translate");
+        return hip_fail(e, "shift down");
     }
   }
   int rflags = (near ? 1 : 0) | (far ? 2 : 0) | (adj ? 4 : 0);
   if (fork) HIPCHK(hipStreamWaitEvent(st, op->ev_join, 0), "join");
   if ((e = stage(op, PIE_STAGE_RECEIVE, st, [&] {
-         return launch_receive<TF, TN>(G, op->I, B, op->NB, op->lv[L].centre, op->lv[L].nb, op->maxpt,
-                                       op->dG[L], op->dKhat, Q, op->kappa_l[L], op->dPart, R, rflags,
-                                       op->phase_mode, y, ld, st);
+         return launch_receive<TF, TN>(op->I, B, op->NB, op->lv[L].nb, op->maxpt, op->maxjoin, op->dG[L],
+                                       op->dKhat, Q, op->kappa_l[L], op->dPart, R, rflags, op->phase_mode, y,
+                                       ld, st);
        })) != hipSuccess)
     return hip_fail(e, "receive");
   return PIE_OK;
@@ -913,6 +1006,9 @@ pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq
   HIPCHK(hipStreamCreateWithFlags(&op->side, hipStreamNonBlocking), "side stream");
   HIPCHK(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming), "fork event");
   HIPCHK(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming), "join event");
+  HIPCHK(hipStreamCreateWithFlags(&op->side2, hipStreamNonBlocking), "side stream");
+  HIPCHK(hipEventCreateWithFlags(&op->ev_agg, hipEventDisableTiming), "fork event");
+  HIPCHK(hipEventCreateWithFlags(&op->ev_il, hipEventDisableTiming), "join event");
   pie_status s = build_operator(op.get(), st);
   if (s) return s;
   *out = op.release();

@@ -55,30 +55,38 @@ def build_ops(w, modes, max_rhs):
 
 
 def time_mvm(op, x, y, steps, warmup):
-    """Timed MVMs without instrumentation (HIP events on the caller's stream
-    around the whole loop), then the same number with per-stage events for
-    the stage breakdown."""
+    """The autotuner picks the launch schedule; the MVM is then captured in
+    a HIP graph and timed over `steps` replays after `warmup` (HIP events on
+    the caller's stream around the replays); eager launches are timed the
+    same way for comparison, then one pass with per-stage events gives the
+    stage breakdown."""
     import torch
-    for _ in range(warmup):
-        op.matvec(x, y)
-    torch.cuda.synchronize()
+    sched, tune_ms = op.autotune(x, y, reps=max(3, steps // 5))
+    g = op.graph(x, y)
     s0 = torch.cuda.Event(enable_timing=True)
     s1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    s0.record()
-    for _ in range(steps):
-        op.matvec(x, y)
-    s1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = s0.elapsed_time(s1) / steps
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        s0.record()
+        for _ in range(steps):
+            fn()
+        s1.record()
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / steps
+
+    ms_graph = timed(g.launch)
+    ms_eager = timed(lambda: op.matvec(x, y))
+    del g
     op.profile(True)
     for _ in range(steps):
         op.matvec(x, y)
     torch.cuda.synchronize()
     stages = op.profile_read()
     op.profile(False)
-    return ms, wall / steps, stages
+    return ms_graph, ms_eager, sched, stages
 
 
 def time_near_only(op, x, y, steps):
@@ -151,10 +159,10 @@ def main():
     res = {}
     for m in modes:
         y = torch.empty_like(x)
-        ms, wall, stages = time_mvm(ops[m], x, y, args.steps, args.warmup)
-        res[m] = dict(ms=ms, wall_ms=wall * 1e3, stages=stages,
+        ms, ms_eager, sched, stages = time_mvm(ops[m], x, y, args.steps, args.warmup)
+        res[m] = dict(ms=ms, ms_eager=ms_eager, schedule=sched, stages=stages,
                       near_alone_ms=time_near_only(ops[m], x, y, args.steps))
-        log(f"[bench] {m}: {ms:.4f} ms/MVM  stages(ms/launch) " +
+        log(f"[bench] {m}: {ms:.4f} ms/MVM (graph), {ms_eager:.4f} eager, schedule {sched}; stages(ms/launch) " +
             " ".join(f"{k}={v[0] / max(1, v[1]):.4f}" for k, v in stages.items() if v[1]) +
             f"  near alone {res[m]['near_alone_ms']:.4f}")
     # --- accuracy gate on sampled rows (the oracle leg provides the reference)
@@ -208,7 +216,8 @@ def main():
         "roofline": roof,
         "dominant_stage": dom,
         "cpu_baseline": cpu,
-        "modes": {m: {"ms_per_mvm": res[m]["ms"], "unknown_rhs_per_s": N * R / (res[m]["ms"] * 1e-3),
+        "modes": {m: {"ms_per_mvm": res[m]["ms"], "ms_per_mvm_eager": res[m]["ms_eager"],
+                      "schedule": res[m]["schedule"], "unknown_rhs_per_s": N * R / (res[m]["ms"] * 1e-3),
                       "max_block_err": (max(res[m]["err"].values()) if "err" in res[m] else None),
                       "gate_1e-3": gate[m],
                       "near_standalone_ms": res[m]["near_alone_ms"],

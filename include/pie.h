@@ -206,6 +206,57 @@ pie_status pie_matvec_far(pie_op* op, const void* x, void* y, int64_t R,
 pie_status pie_profile_enable(pie_op* op, int32_t on);
 pie_status pie_profile_read(pie_op* op, double* ms, int64_t* launches);
 
+/* ----------------------------------------------------------- schedule --
+ * Placement of the MVM's kernels on streams.  Every schedule computes the
+ * same result bit for bit: neither the arithmetic nor its order depends on
+ * it, only the overlap of independent stages.
+ *   near_fork: PIE_NEAR_SERIAL runs the near field, then the far chain, on
+ *     the caller's stream; PIE_NEAR_FORK_START runs the near field on a
+ *     second stream from the start; PIE_NEAR_FORK_AFTER_AGGREGATE forks it
+ *     after the finest-level aggregation.  The reception joins it.
+ *   il_fork: 1 runs the finest level's interaction-list translation on a
+ *     third stream, concurrent with the upward shifts.
+ *   max_chunk: widest group of RHS columns per kernel pass (1, 2 or 4; the
+ *     operator's own limit from its LDS budget applies).
+ * Default: PIE_NEAR_FORK_START, il_fork 1, max_chunk 4. */
+#define PIE_NEAR_SERIAL 0
+#define PIE_NEAR_FORK_START 1
+#define PIE_NEAR_FORK_AFTER_AGGREGATE 2
+typedef struct pie_schedule {
+  int32_t version; /* must be 1 */
+  int32_t near_fork;
+  int32_t il_fork;
+  int32_t max_chunk;
+} pie_schedule;
+pie_status pie_schedule_get(const pie_op* op, pie_schedule* out);
+/* PIE_ERR_ARG for an unknown near_fork, il_fork not 0/1 or max_chunk not
+ * 1, 2 or 4. */
+pie_status pie_schedule_set(pie_op* op, const pie_schedule* sch);
+
+/* Autotuner: times every distinct schedule on R right-hand sides (one
+ * warm-up, then reps MVMs each, HIP events on stream), keeps the fastest
+ * on the operator and returns it in *chosen and its time per MVM in *ms
+ * (either may be NULL).  x, y: caller-owned device complex128 [N][R] work
+ * vectors (x is read, y overwritten).  Stage profiling must be off.
+ * Synchronizes the stream. */
+pie_status pie_autotune(pie_op* op, const void* x, void* y, int64_t R,
+                        int32_t reps, void* stream, pie_schedule* chosen,
+                        double* ms);
+
+/* ------------------------------------------------------------- graphs --
+ * A captured MVM: the kernels of y = Z x (adjoint = 0) or Z^H x for fixed
+ * x, y and R, with the operator's schedule at capture time, recorded once
+ * into a HIP graph (captured on a private stream; the operator's side
+ * streams join it through events) and replayed with one launch.  A replay
+ * uses the operator's workspace: replays and other calls on the same
+ * operator must not overlap.  Stage profiling must be off when capturing.
+ * The graph must be destroyed before its operator. */
+typedef struct pie_graph pie_graph;
+pie_status pie_graph_create(pie_op* op, const void* x, void* y, int64_t R,
+                            int32_t adjoint, pie_graph** out);
+pie_status pie_graph_launch(pie_graph* g, void* stream);
+void pie_graph_destroy(pie_graph* g);
+
 /* ---------------------------------------------------------------- RHS --
  * Plane waves E^inc = amp_r pol_r exp(i k khat_r . r) (E0 = 1 V/m scale).
  * khat, pol: host double [R][3] (unit, orthogonal); amp: host complex128 [R].

@@ -27,6 +27,9 @@ PIE_ERR_UNSUPPORTED = -7
 PIE_WARN_NOT_CONVERGED = 1
 PIE_FP32 = 32
 PIE_FP64 = 64
+PIE_NEAR_SERIAL = 0
+PIE_NEAR_FORK_START = 1
+PIE_NEAR_FORK_AFTER_AGGREGATE = 2
 
 TQ = dict(NBOX=1, COORDS=2, PARENT=3, PERM=4, BOXPTR=5, NEAR_PTR=6, NEAR_IDX=7,
           IL_PTR=8, IL_SRC=9, IL_OFF=10)
@@ -41,6 +44,8 @@ EXPORTS = [
     "pie_operator_level", "pie_matvec", "pie_matvec_near", "pie_matvec_far",
     "pie_rhs_planewave", "pie_solve_opts_default", "pie_solve", "pie_farfield",
     "pie_profile_enable", "pie_profile_read", "pie_farfield_adjoint",
+    "pie_schedule_get", "pie_schedule_set", "pie_autotune",
+    "pie_graph_create", "pie_graph_launch", "pie_graph_destroy",
 ]
 STAGES = ["permute", "near", "aggregate", "shift_up", "translate", "receive", "shift_down"]
 
@@ -50,6 +55,11 @@ class pie_options(ctypes.Structure):
                 ("far_prec", ctypes.c_int32), ("tau", ctypes.c_int32), ("x", ctypes.c_double),
                 ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32),
                 ("max_rhs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pie_schedule(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int32), ("near_fork", ctypes.c_int32),
+                ("il_fork", ctypes.c_int32), ("max_chunk", ctypes.c_int32)]
 
 
 class pie_solve_opts(ctypes.Structure):
@@ -102,6 +112,12 @@ def lib():
         "pie_profile_enable": (I32, [P, I32]),
         "pie_profile_read": (I32, [P, P, P]),
         "pie_farfield_adjoint": (I32, [P, P, I64, P, I64, P, P]),
+        "pie_schedule_get": (I32, [P, ctypes.POINTER(pie_schedule)]),
+        "pie_schedule_set": (I32, [P, ctypes.POINTER(pie_schedule)]),
+        "pie_autotune": (I32, [P, P, P, I64, I32, P, ctypes.POINTER(pie_schedule), pD]),
+        "pie_graph_create": (I32, [P, P, P, I64, I32, ctypes.POINTER(P)]),
+        "pie_graph_launch": (I32, [P, P]),
+        "pie_graph_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

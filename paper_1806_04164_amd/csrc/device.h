@@ -62,56 +62,6 @@ __device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c)
   sincos(x, s, c);
 }
 
-// exp(i th) = (cos th, sin th) for the small phase arguments of the
-// radiation and receiving patterns: Taylor series of cos and sin (Horner in
-// th^2), with the number of terms chosen on the host from the largest
-// |th| of the operator so that the first omitted term is below the type's
-// rounding:
-//   FP64, NT = 5 (through th^9):  |th| <= 0.1, omitted 0.1^10/10! ~ 3e-17
-//   FP64, NT = 9 (through th^17): |th| <= 0.5, omitted 0.5^18/18! ~ 6e-22
-//   FP32, NT = 4 (through th^7):  |th| <= 0.2, omitted 0.2^8/8!  ~ 6e-11
-//   FP32, NT = 6 (through th^11): |th| <= 0.5, omitted 0.5^12/12! ~ 5e-13
-// Operators whose bound exceeds 1/2 use the library sincos throughout.
-template <typename T, int NT>
-struct PhaseLimit;
-template <> struct PhaseLimit<double, 5> { static constexpr double v = 0.1; };
-template <> struct PhaseLimit<double, 9> { static constexpr double v = 0.5; };
-template <> struct PhaseLimit<float, 4> { static constexpr float v = 0.2f; };
-template <> struct PhaseLimit<float, 6> { static constexpr float v = 0.5f; };
-
-// 1/(2k)! and 1/(2k+1)! for k = 0..8
-__device__ __forceinline__ constexpr double inv_fact_even(int k) {
-  return k == 0 ? 1.0 : k == 1 ? 1.0 / 2.0 : k == 2 ? 1.0 / 24.0 : k == 3 ? 1.0 / 720.0
-       : k == 4 ? 1.0 / 40320.0 : k == 5 ? 1.0 / 3628800.0 : k == 6 ? 1.0 / 479001600.0
-       : k == 7 ? 1.0 / 87178291200.0 : 1.0 / 20922789888000.0;
-}
-__device__ __forceinline__ constexpr double inv_fact_odd(int k) {
-  return k == 0 ? 1.0 : k == 1 ? 1.0 / 6.0 : k == 2 ? 1.0 / 120.0 : k == 3 ? 1.0 / 5040.0
-       : k == 4 ? 1.0 / 362880.0 : k == 5 ? 1.0 / 39916800.0 : k == 6 ? 1.0 / 6227020800.0
-       : k == 7 ? 1.0 / 1307674368000.0 : 1.0 / 355687428096000.0;
-}
-
-// NT = 0: library sincos (used when the host bound exceeds 1/2); NT > 0:
-// the polynomial only -- the host guarantees |th| within the bound, so there
-// is no run-time fallback (and no register cost for one).
-template <typename T, int NT>
-__device__ __forceinline__ void phase(T th, T* s, T* c) {
-  if constexpr (NT == 0) {
-    sincos_t<T>(th, s, c);
-  } else {
-    const T t2 = -th * th;
-    T cc = (T)inv_fact_even(NT - 1);
-    T ss = (T)inv_fact_odd(NT - 1);
-#pragma unroll
-    for (int k = NT - 2; k >= 0; --k) {
-      cc = fma(cc, t2, (T)inv_fact_even(k));
-      ss = fma(ss, t2, (T)inv_fact_odd(k));
-    }
-    *c = cc;
-    *s = ss * th;
-  }
-}
-
 // Workgroup -> box index with consecutive boxes (Morton order, i.e. spatial
 // neighbours) on the same XCD: workgroups are dispatched round-robin over
 // the 8 XCDs, so workgroup w runs on XCD w % 8; box = (w % 8) * per + w / 8.

@@ -15,122 +15,153 @@
 namespace pie {
 
 // ---------------------------------------------------------------------------
-// Finest-level aggregation.  Every (box, triangle) incidence contributes
-// seven quadrature points; per point the source density
-//   W_i * (J(r_i), sigma, div J + w^2 eps0 sigma),  J = sum x_n s_n (r_i - p_n)
-// is formed from x (independent loads of the incidence tables, then of x),
-// then for every sample q
-//   S(q) += density * exp(-i kappa khat_q . (r_i - C_box)).
-// Workgroup = one finest box; stage 1 threads over points, stage 2 over
-// (q, point slice), stage 3 adds the slices in a fixed order.
+// Finest-level radiation patterns through per-incidence moments.  For a
+// (box, triangle) incidence j with quadrature points r_i, weights W_i and
+// o_i = r_i - C_box, the moment table holds (set-up, FP64 phases)
+//   M0_j(q) = sum_i W_i e_i(q),   M1_j(q) = sum_i W_i o_i e_i(q),
+//   e_i(q) = exp(-i kappa khat_q . o_i).
+// An RWG half s (r - p) on the triangle radiates s (M1 - (p - C) M0), its
+// divergence d M0 and a pulse M0, so with the incidence coefficients
+//   a = sum_k x_k s_k,  b = sum_k x_k s_k (p_k - C),  xp = x_pulse,
+//   cu = sum_k x_k d_k + w^2 eps0 xp
+// the box patterns are
+//   S_J(q) += a M1 - b M0,  S_sigma(q) += xp M0,  S_u(q) += cu M0.
 // ---------------------------------------------------------------------------
-template <typename TF, int RC, int NT>
+template <typename TF>
+__global__ void __launch_bounds__(128) k_moments(const double* __restrict__ pw, const double* __restrict__ khat,
+                                                 int Q, double kappa, cx<TF>* __restrict__ M) {
+  const int j = blockIdx.x;
+  const double* p = pw + 28 * (size_t)j;
+  double o[7][3], w[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o[i][c] = p[4 * i + c];
+    w[i] = p[4 * i + 3];
+  }
+  for (int q = threadIdx.x; q < Q; q += blockDim.x) {
+    const double kx = kappa * khat[3 * q], ky = kappa * khat[3 * q + 1], kz = kappa * khat[3 * q + 2];
+    cx<double> m0 = mk(0.0, 0.0), m1[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      double sn, cs;
+      sincos(kx * o[i][0] + ky * o[i][1] + kz * o[i][2], &sn, &cs);
+      const cx<double> e = mk(w[i] * cs, -w[i] * sn);
+      m0 = m0 + e;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) m1[c] = m1[c] + o[i][c] * e;
+    }
+    cx<TF>* out = M + ((size_t)j * Q + q) * 4;
+    out[0] = mk((TF)m0.re, (TF)m0.im);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[1 + c] = mk((TF)m1[c].re, (TF)m1[c].im);
+  }
+}
+
+// Workgroup = one finest box.  Stage 1: thread per (incidence, RHS) forms
+// the coefficients (a, -b, xp, cu) in LDS.  Stage 2: thread (g, q) adds the
+// incidences j = g (mod nsplit) in order, four incidences' moments in flight;
+// stage 3 adds the nsplit slices in a fixed order.
+template <typename TF, int RC>
 __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<double>* __restrict__ x, int ldx,
-                                                   const TF* __restrict__ khat, int Q, TF kappa, double w2e,
-                                                   int conjx, int nsplit, cx<TF>* __restrict__ S) {
+                                                   const cx<TF>* __restrict__ M, int Q, double w2e, int conjx,
+                                                   int nsplit, cx<TF>* __restrict__ S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_box(blockIdx.x, nbox);
   if (b < 0) return;
-  const int j0 = I.ptr[b], j1 = I.ptr[b + 1];
-  const int npt = 7 * (j1 - j0);
+  const int j0 = I.ptr[b], ni = I.ptr[b + 1] - j0;
   constexpr int ncol = 5 * RC;
-  cx<TF>* dens = (cx<TF>*)smem;                              // [npt][5][RC]
-  cx<TF>* part = dens + (size_t)npt * ncol;                  // [nsplit][Q][5][RC]
-  TF* poff = (TF*)(part + (size_t)nsplit * Q * ncol);        // [npt][4]
-  for (int p = threadIdx.x; p < npt; p += blockDim.x) {
-    const int j = j0 + p / 7;
-    const double* pw = I.pw + 4 * ((size_t)7 * j0 + p);
-    const double o[3] = {pw[0], pw[1], pw[2]}, w = pw[3];
+  cx<TF>* cf = (cx<TF>*)smem;                      // [ni][6][RC]: a, -bx, -by, -bz, xp, cu
+  cx<TF>* part = cf + (size_t)ni * 6 * RC;         // [nsplit - 1][Q][5][RC]
+  for (int e = threadIdx.x; e < ni * RC; e += blockDim.x) {
+    const int jl = e / RC, r = e - jl * RC;
+    const size_t j = (size_t)(j0 + jl);
     int xc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xc[k] = I.xc[4 * j + k];
     double sv[3], dv[3], pv[3][3];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) xc[k] = I.xc[4 * (size_t)j + k];
+    for (int k = 0; k < 3; ++k) {
+      sv[k] = I.rs[3 * j + k];
+      dv[k] = I.rd[3 * j + k];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pv[k][c] = I.pv[9 * j + 3 * k + c];
+    }
+    cx<double> xv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      xv[k] = xc[k] >= 0 ? x[(size_t)xc[k] * ldx + r] : mk(0.0, 0.0);
+      if (conjx) xv[k].im = -xv[k].im;
+    }
+    cx<double> a = mk(0.0, 0.0), bb[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)}, cu = mk(0.0, 0.0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      sv[k] = I.rs[3 * (size_t)j + k];
-      dv[k] = I.rd[3 * (size_t)j + k];
+      a = a + sv[k] * xv[k];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) pv[k][c] = I.pv[9 * (size_t)j + 3 * k + c];
+      for (int c = 0; c < 3; ++c) bb[c] = bb[c] + (sv[k] * pv[k][c]) * xv[k];
+      cu = cu + dv[k] * xv[k];
     }
-    poff[4 * p + 0] = (TF)o[0];
-    poff[4 * p + 1] = (TF)o[1];
-    poff[4 * p + 2] = (TF)o[2];
-    poff[4 * p + 3] = (TF)0;
+    cu = cu + w2e * xv[3];
+    cx<TF>* o = cf + (size_t)jl * 6 * RC + r;
+    o[0] = mk((TF)a.re, (TF)a.im);
 #pragma unroll
-    for (int r = 0; r < RC; ++r) {
-      cx<double> xv[4];
+    for (int c = 0; c < 3; ++c) o[(1 + c) * RC] = mk((TF)-bb[c].re, (TF)-bb[c].im);
+    o[4 * RC] = mk((TF)xv[3].re, (TF)xv[3].im);
+    o[5 * RC] = mk((TF)cu.re, (TF)cu.im);
+  }
+  __syncthreads();
+  const int gsz = Q;
+  const int g = threadIdx.x / gsz, q = threadIdx.x - g * gsz;
+  const bool act = g < nsplit;
+  cx<TF> acc[ncol];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        xv[k] = xc[k] >= 0 ? x[(size_t)xc[k] * ldx + r] : mk(0.0, 0.0);
-        if (conjx) xv[k].im = -xv[k].im;
+  for (int c = 0; c < ncol; ++c) acc[c] = mk<TF>(0, 0);
+  if (act) {
+    constexpr int U = 4;
+    for (int jl = g; jl < ni; jl += U * nsplit) {
+      cx<TF> m[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int jj = jl + u * nsplit;
+        const cx<TF>* mp = M + ((size_t)(j0 + (jj < ni ? jj : jl)) * Q + q) * 4;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) m[u][t] = mp[t];
       }
-      cx<double> J[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
-      cx<double> D = mk(0.0, 0.0);
+      __builtin_amdgcn_sched_barrier(0);  // keep the incidences' loads in flight together
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
+      for (int u = 0; u < U; ++u) {
+        const int jj = jl + u * nsplit;
+        if (jj < ni) {
+          const cx<TF>* c6 = cf + (size_t)jj * 6 * RC;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) J[c] = J[c] + (sv[k] * (o[c] - pv[k][c])) * xv[k];
-        D = D + dv[k] * xv[k];
+          for (int r = 0; r < RC; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              cfma(acc[c * RC + r], c6[r], m[u][1 + c]);
+              cfma(acc[c * RC + r], c6[(1 + c) * RC + r], m[u][0]);
+            }
+            cfma(acc[3 * RC + r], c6[4 * RC + r], m[u][0]);
+            cfma(acc[4 * RC + r], c6[5 * RC + r], m[u][0]);
+          }
+        }
       }
-      const cx<double> sg = xv[3];
-      cx<TF>* dp = dens + (size_t)p * ncol;
+    }
+    if (g > 0) {
+      cx<TF>* pp = part + ((size_t)(g - 1) * Q + q) * ncol;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) dp[c * RC + r] = mk((TF)(w * J[c].re), (TF)(w * J[c].im));
-      dp[3 * RC + r] = mk((TF)(w * sg.re), (TF)(w * sg.im));
-      const cx<double> uu = D + w2e * sg;
-      dp[4 * RC + r] = mk((TF)(w * uu.re), (TF)(w * uu.im));
+      for (int c = 0; c < ncol; ++c) pp[c] = acc[c];
     }
   }
   __syncthreads();
-  if (threadIdx.x < nsplit * Q) {
-    const int q = threadIdx.x % Q, part_id = threadIdx.x / Q;
-    const TF kx = kappa * khat[3 * q], ky = kappa * khat[3 * q + 1], kz = kappa * khat[3 * q + 2];
-    cx<TF> acc[ncol];
+  if (act && g == 0) {
+    for (int h = 1; h < nsplit; ++h) {
+      const cx<TF>* pp = part + ((size_t)(h - 1) * Q + q) * ncol;
 #pragma unroll
-    for (int c = 0; c < ncol; ++c) acc[c] = mk<TF>(0, 0);
-    // two points per step (same per-accumulator order as one at a time)
-    int p = part_id;
-    for (; p + nsplit < npt; p += 2 * nsplit) {
-      const TF* o0 = poff + 4 * p;
-      const TF* o1 = poff + 4 * (p + nsplit);
-      cx<TF> d0[ncol], d1[ncol];
-#pragma unroll
-      for (int c = 0; c < ncol; ++c) {
-        d0[c] = dens[(size_t)p * ncol + c];
-        d1[c] = dens[(size_t)(p + nsplit) * ncol + c];
-      }
-      const TF th0 = kx * o0[0] + ky * o0[1] + kz * o0[2];
-      const TF th1 = kx * o1[0] + ky * o1[1] + kz * o1[2];
-      TF s0, c0, s1, c1;
-      phase<TF, NT>(th0, &s0, &c0);
-      phase<TF, NT>(th1, &s1, &c1);
-      const cx<TF> e0 = mk(c0, -s0), e1 = mk(c1, -s1);
-#pragma unroll
-      for (int c = 0; c < ncol; ++c) {
-        cfma(acc[c], d0[c], e0);
-        cfma(acc[c], d1[c], e1);
-      }
+      for (int c = 0; c < ncol; ++c) acc[c] = acc[c] + pp[c];
     }
-    if (p < npt) {
-      const TF* o0 = poff + 4 * p;
-      const TF th0 = kx * o0[0] + ky * o0[1] + kz * o0[2];
-      TF s0, c0;
-      phase<TF, NT>(th0, &s0, &c0);
-      const cx<TF> e0 = mk(c0, -s0);
+    cx<TF>* o = S + ((size_t)b * Q + q) * ncol;
 #pragma unroll
-      for (int c = 0; c < ncol; ++c) cfma(acc[c], dens[(size_t)p * ncol + c], e0);
-    }
-    cx<TF>* pp = part + ((size_t)part_id * Q + q) * ncol;
-#pragma unroll
-    for (int c = 0; c < ncol; ++c) pp[c] = acc[c];
-  }
-  __syncthreads();
-  // fixed-order combination of the partial sums; dens is [comp][RC] = col order
-  for (int e = threadIdx.x; e < Q * ncol; e += blockDim.x) {
-    const int q = e / ncol, c = e - q * ncol;
-    cx<TF> v = part[(size_t)q * ncol + c];
-    for (int h = 1; h < nsplit; ++h) v = v + part[((size_t)h * Q + q) * ncol + c];
-    S[((size_t)b * Q + q) * ncol + c] = v;
+    for (int c = 0; c < ncol; ++c) o[c] = acc[c];
   }
 }
 
@@ -385,32 +416,32 @@ __global__ void __launch_bounds__(512) k_translate(DevLevel Lv, const cx<TF>* __
 
 // ---------------------------------------------------------------------------
 // Reception at the finest level and join with the near-field partial sums.
-// Per quadrature point the incoming field
-//   fld(r_i) = W_i sum_q exp(+i kappa khat_q.(r_i - C_box)) G(q)
-// is formed; then every unknown of the box takes its testing integral:
-//   RWG:   y += mu0 s (r_i - p).fld_J + d fld_sigma   (both halves)
-//   pulse: y += fld_u,
-// adds its near-field partial sums in a fixed order (slot lists staged in
-// LDS), and is written to the canonical position (conjugated for the
-// adjoint).  Point offsets are kept in FP64 for the testing integrals.
+// Receiving patterns are the conjugates of the radiation patterns, so with
+// the moments of each incidence j
+//   A = sum_q conj(M1).G_J,  B = sum_q conj(M0) G_J,
+//   Cs = sum_q conj(M0) G_sigma,  Du = sum_q conj(M0) G_u,
+// an RWG half s (r - p), divergence d, tests to  mu0 s (A - (p - C).B) + d Cs
+// and a pulse to Du.  Thread (incidence, quarter of the samples) sums its
+// quarter; the four quarters are added by a fixed butterfly.  Each unknown
+// then adds its halves, its near-field partial sums in a fixed order (slot
+// lists staged in LDS), and is written to its canonical position
+// (conjugated for the adjoint).
 // ---------------------------------------------------------------------------
-template <typename TF, typename TN, int RC, int NT>
+constexpr int RECV_SLICES = 4;
+template <typename TF, typename TN, int RC>
 __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear NB, int nbox,
-                                                 const cx<TF>* __restrict__ Gin, const TF* __restrict__ khat,
-                                                 int Q, TF kappa, const cx<TN>* __restrict__ part, int flags,
+                                                 const cx<TF>* __restrict__ Gin, const cx<TF>* __restrict__ M,
+                                                 int Q, const cx<TN>* __restrict__ part, int flags,
                                                  cx<double>* __restrict__ y, int ldy) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_box(blockIdx.x, nbox);
   if (b < 0) return;
-  const int j0 = I.ptr[b], j1 = I.ptr[b + 1];
-  const int npt = 7 * (j1 - j0);
+  const int j0 = I.ptr[b], ni = I.ptr[b + 1] - j0;
   constexpr int ncol = 5 * RC;
   const bool do_far = flags & 2, do_near = flags & 1, conj_out = flags & 4;
-  double* po = (double*)smem;                              // [npt][4] r_i - C, W_i
-  cx<TF>* fld = (cx<TF>*)(po + 4 * (size_t)npt);            // [npt][5][RC]
-  cx<TF>* Gs = fld + (size_t)npt * ncol;                   // [Q][5][RC]
-  TF* kh = (TF*)(Gs + (size_t)Q * ncol);                   // [Q][4] kappa * khat
-  int32_t* slots = (int32_t*)(kh + 4 * Q);                 // near-field partial-sum slots
+  cx<TF>* Gs = (cx<TF>*)smem;                              // [Q][5][RC]
+  cx<TF>* red = Gs + (size_t)Q * ncol;                     // [ni][6][RC]: A, Bx, By, Bz, Cs, Du
+  int32_t* slots = (int32_t*)(red + (size_t)ni * 6 * RC);  // near-field partial-sum slots
   const double mu0 = 4.0e-7 * 3.14159265358979323846;
   const int nrow = do_near ? NB.row_ptr[b + 1] - NB.row_ptr[b] : 0;
   const int nslot = do_near ? nrow + NB.col_ptr[b + 1] - NB.col_ptr[b] : 0;
@@ -419,39 +450,50 @@ __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear N
   if (do_far) {
     const cx<TF>* g = Gin + (size_t)b * Q * ncol;
     for (int e = threadIdx.x; e < Q * ncol; e += blockDim.x) Gs[e] = g[e];
-    for (int q = threadIdx.x; q < Q; q += blockDim.x) {
-      kh[4 * q + 0] = kappa * khat[3 * q];
-      kh[4 * q + 1] = kappa * khat[3 * q + 1];
-      kh[4 * q + 2] = kappa * khat[3 * q + 2];
-      kh[4 * q + 3] = 0;
-    }
-    const double* pw = I.pw + 28 * (size_t)j0;
-    for (int e = threadIdx.x; e < 4 * npt; e += blockDim.x) po[e] = pw[e];
   }
   __syncthreads();
   if (do_far) {
-    for (int p = threadIdx.x; p < npt; p += blockDim.x) {
-      cx<TF> acc[ncol];
+    const int qs = (Q + RECV_SLICES - 1) / RECV_SLICES;
+    for (int base = 0; base < ni * RECV_SLICES; base += blockDim.x) {
+      const int t = base + threadIdx.x;
+      const int jl = t / RECV_SLICES, sl = t - jl * RECV_SLICES;
+      const bool act = jl < ni;
+      cx<TF> acc[6 * RC];
 #pragma unroll
-      for (int c = 0; c < ncol; ++c) acc[c] = mk<TF>(0, 0);
-      const TF ox = (TF)po[4 * p], oy = (TF)po[4 * p + 1], oz = (TF)po[4 * p + 2];
-#pragma unroll 2
-      for (int q = 0; q < Q; ++q) {
-        const TF* k4 = kh + 4 * q;
-        cx<TF> gq[ncol];
+      for (int c = 0; c < 6 * RC; ++c) acc[c] = mk<TF>(0, 0);
+      if (act) {
+        const int qa = sl * qs, qb = min(Q, qa + qs);
+        const cx<TF>* mp = M + ((size_t)(j0 + jl) * Q) * 4;
+        for (int q = qa; q < qb; ++q) {
+          cx<TF> m[4];
 #pragma unroll
-        for (int c = 0; c < ncol; ++c) gq[c] = Gs[(size_t)q * ncol + c];
-        const TF th = k4[0] * ox + k4[1] * oy + k4[2] * oz;
-        TF sn, cs;
-        phase<TF, NT>(th, &sn, &cs);
-        const cx<TF> e = mk(cs, sn);
+          for (int k = 0; k < 4; ++k) m[k] = conj(mp[4 * (size_t)q + k]);
+          const cx<TF>* gq = Gs + (size_t)q * ncol;
 #pragma unroll
-        for (int c = 0; c < ncol; ++c) cfma(acc[c], e, gq[c]);
+          for (int r = 0; r < RC; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const cx<TF> gc = gq[c * RC + r];
+              cfma(acc[r], m[1 + c], gc);
+              cfma(acc[(1 + c) * RC + r], m[0], gc);
+            }
+            cfma(acc[4 * RC + r], m[0], gq[3 * RC + r]);
+            cfma(acc[5 * RC + r], m[0], gq[4 * RC + r]);
+          }
+        }
       }
-      const TF w = (TF)po[4 * p + 3];
-      cx<TF>* fp = fld + (size_t)p * ncol;
+      // (s0 + s1) + (s2 + s3) across the four lanes of an incidence
 #pragma unroll
-      for (int c = 0; c < ncol; ++c) fp[c] = w * acc[c];
+      for (int c = 0; c < 6 * RC; ++c) {
+        acc[c].re += __shfl_xor(acc[c].re, 1);
+        acc[c].im += __shfl_xor(acc[c].im, 1);
+        acc[c].re += __shfl_xor(acc[c].re, 2);
+        acc[c].im += __shfl_xor(acc[c].im, 2);
+      }
+      if (act && sl == 0) {
+#pragma unroll
+        for (int c = 0; c < 6 * RC; ++c) red[(size_t)jl * 6 * RC + c] = acc[c];
+      }
     }
     __syncthreads();
   }
@@ -465,34 +507,22 @@ __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear N
       if (cu < B.ne) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int jl = I.uj[2 * u + h] - j0;
+          const cx<TF>* rv = red + (size_t)(I.uj[2 * u + h] - j0) * 6 * RC + r;
           const double s = I.us[2 * u + h], d = I.ud[2 * u + h];
-          const double pv[3] = {I.upv[6 * (size_t)u + 3 * h], I.upv[6 * (size_t)u + 3 * h + 1],
-                                I.upv[6 * (size_t)u + 3 * h + 2]};
+          cx<double> t = mk((double)rv[0].re, (double)rv[0].im);
 #pragma unroll
-          for (int i = 0; i < 7; ++i) {
-            const double* o = po + 4 * (7 * jl + i);
-            const cx<TF>* f = fld + (size_t)(7 * jl + i) * ncol;
-            cx<double> a = mk(0.0, 0.0);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const double dd = mu0 * s * (o[c] - pv[c]);
-              a.re += dd * (double)f[c * RC + r].re;
-              a.im += dd * (double)f[c * RC + r].im;
-            }
-            a.re += d * (double)f[3 * RC + r].re;
-            a.im += d * (double)f[3 * RC + r].im;
-            val = val + a;
+          for (int c = 0; c < 3; ++c) {
+            const double pc = I.upv[6 * (size_t)u + 3 * h + c];
+            t.re -= pc * (double)rv[(1 + c) * RC].re;
+            t.im -= pc * (double)rv[(1 + c) * RC].im;
           }
+          val.re += mu0 * s * t.re + d * (double)rv[4 * RC].re;
+          val.im += mu0 * s * t.im + d * (double)rv[4 * RC].im;
         }
       } else {
-        const int jl = I.uj[2 * u] - j0;
-        const cx<TF>* fp = fld + (size_t)jl * 7 * ncol;
-#pragma unroll
-        for (int i = 0; i < 7; ++i) {
-          val.re += (double)fp[(size_t)i * ncol + 4 * RC + r].re;
-          val.im += (double)fp[(size_t)i * ncol + 4 * RC + r].im;
-        }
+        const cx<TF>* rv = red + (size_t)(I.uj[2 * u] - j0) * 6 * RC + r;
+        val.re += (double)rv[5 * RC].re;
+        val.im += (double)rv[5 * RC].im;
       }
     }
     if (do_near) {
@@ -532,37 +562,30 @@ __global__ void k_permute_in(const cx<double>* __restrict__ x, int ldx, const in
 }
 
 // ------------------------------------------------------------- launchers --
-size_t aggregate_smem(int maxpt, int Q, int nsplit, int RC, int tf_bytes) {
-  return (size_t)maxpt * 5 * RC * 2 * tf_bytes + (size_t)nsplit * Q * 5 * RC * 2 * tf_bytes +
-         (size_t)maxpt * 4 * tf_bytes + 16;
+size_t aggregate_smem(int maxinc, int Q, int nsplit, int RC, int tf_bytes) {
+  return (size_t)maxinc * 6 * RC * 2 * tf_bytes + (size_t)(nsplit - 1) * Q * 5 * RC * 2 * tf_bytes + 16;
 }
-size_t receive_smem(int maxpt, int Q, int maxjoin, int RC, int tf_bytes) {
-  return (size_t)maxpt * 4 * 8 + (size_t)maxpt * 5 * RC * 2 * tf_bytes + (size_t)Q * 5 * RC * 2 * tf_bytes +
-         (size_t)Q * 4 * tf_bytes + (size_t)maxjoin * 4 + 16;
-}
-
-template <typename TF, int RC, int NT>
-static void agg_launch(const DevInc& I, int nb, int maxpt, const void* x, int ldx, const void* khat, int Q,
-                       double kappa, double w2e, int conjx, int nsplit, void* S, hipStream_t st) {
-  size_t sm = aggregate_smem(maxpt, Q, nsplit, RC, sizeof(TF));
-  hipLaunchKernelGGL((k_aggregate<TF, RC, NT>), dim3(xcd_grid(nb)), dim3(256), sm, st, I, nb, (const cx<double>*)x,
-                     ldx, (const TF*)khat, Q, (TF)kappa, w2e, conjx, nsplit, (cx<TF>*)S);
+size_t receive_smem(int maxinc, int Q, int maxjoin, int RC, int tf_bytes) {
+  return (size_t)Q * 5 * RC * 2 * tf_bytes + (size_t)maxinc * 6 * RC * 2 * tf_bytes + (size_t)maxjoin * 4 + 16;
 }
 
 template <typename TF>
-hipError_t launch_aggregate(const DevInc& I, int nb, int maxpt, const void* x, int ldx, int R, const void* khat,
-                            int Q, double kappa, double w2e, int conjx, int nsplit, int phase_mode, void* S,
-                            hipStream_t st) {
-  constexpr int NS = sizeof(TF) == 8 ? 5 : 4, NL = sizeof(TF) == 8 ? 9 : 6;
+hipError_t launch_moments(const double* pw, int ninc, const double* khat64, int Q, double kappa, void* M,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_moments<TF>, dim3(ninc), dim3(128), 0, st, pw, khat64, Q, kappa, (cx<TF>*)M);
+  return hipGetLastError();
+}
+
+template <typename TF>
+hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, int ldx, int R, const void* M,
+                            int Q, double w2e, int conjx, int nsplit, void* S, hipStream_t st) {
   if (R != 1 && R != 2 && R != 4) return hipErrorInvalidValue;
-#define AGG(RC_, NT_) agg_launch<TF, RC_, NT_>(I, nb, maxpt, x, ldx, khat, Q, kappa, w2e, conjx, nsplit, S, st)
-  if (phase_mode == 1) {
-    if (R == 1) AGG(1, NS); else if (R == 2) AGG(2, NS); else AGG(4, NS);
-  } else if (phase_mode == 2) {
-    if (R == 1) AGG(1, NL); else if (R == 2) AGG(2, NL); else AGG(4, NL);
-  } else {
-    if (R == 1) AGG(1, 0); else if (R == 2) AGG(2, 0); else AGG(4, 0);
-  }
+  if (nsplit * Q > 256) return hipErrorInvalidValue;
+#define AGG(RC_)                                                                                               \
+  hipLaunchKernelGGL((k_aggregate<TF, RC_>), dim3(xcd_grid(nb)), dim3(256),                                    \
+                     aggregate_smem(maxinc, Q, nsplit, RC_, sizeof(TF)), st, I, nb, (const cx<double>*)x, ldx, \
+                     (const cx<TF>*)M, Q, w2e, conjx, nsplit, (cx<TF>*)S)
+  if (R == 1) AGG(1); else if (R == 2) AGG(2); else AGG(4);
 #undef AGG
   return hipGetLastError();
 }
@@ -608,31 +631,16 @@ hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, vo
   return hipGetLastError();
 }
 
-template <typename TF, typename TN, int RC, int NT>
-static void rec_launch(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxpt, int maxjoin,
-                       const void* Gin, const void* khat, int Q, double kappa, const void* part, int flags, void* y,
-                       int ldy, hipStream_t st) {
-  size_t sm = receive_smem(maxpt, Q, maxjoin, RC, sizeof(TF));
-  hipLaunchKernelGGL((k_receive<TF, TN, RC, NT>), dim3(xcd_grid(nb)), dim3(256), sm, st, I, B, NB, nb,
-                     (const cx<TF>*)Gin, (const TF*)khat, Q, (TF)kappa, (const cx<TN>*)part, flags,
-                     (cx<double>*)y, ldy);
-}
-
 template <typename TF, typename TN>
-hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxpt, int maxjoin,
-                          const void* Gin, const void* khat, int Q, double kappa, const void* part, int R,
-                          int flags, int phase_mode, void* y, int ldy, hipStream_t st) {
-  constexpr int NS = sizeof(TF) == 8 ? 5 : 4, NL = sizeof(TF) == 8 ? 9 : 6;
+hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxinc, int maxjoin,
+                          const void* Gin, const void* M, int Q, const void* part, int R, int flags, void* y,
+                          int ldy, hipStream_t st) {
   if (R != 1 && R != 2 && R != 4) return hipErrorInvalidValue;
-#define REC(RC_, NT_) \
-  rec_launch<TF, TN, RC_, NT_>(I, B, NB, nb, maxpt, maxjoin, Gin, khat, Q, kappa, part, flags, y, ldy, st)
-  if (phase_mode == 1) {
-    if (R == 1) REC(1, NS); else if (R == 2) REC(2, NS); else REC(4, NS);
-  } else if (phase_mode == 2) {
-    if (R == 1) REC(1, NL); else if (R == 2) REC(2, NL); else REC(4, NL);
-  } else {
-    if (R == 1) REC(1, 0); else if (R == 2) REC(2, 0); else REC(4, 0);
-  }
+#define REC(RC_)                                                                                            \
+  hipLaunchKernelGGL((k_receive<TF, TN, RC_>), dim3(xcd_grid(nb)), dim3(256),                               \
+                     receive_smem(maxinc, Q, maxjoin, RC_, sizeof(TF)), st, I, B, NB, nb, (const cx<TF>*)Gin, \
+                     (const cx<TF>*)M, Q, (const cx<TN>*)part, flags, (cx<double>*)y, ldy)
+  if (R == 1) REC(1); else if (R == 2) REC(2); else REC(4);
 #undef REC
   return hipGetLastError();
 }
@@ -647,8 +655,9 @@ hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N,
 }
 
 #define INST_F(TF)                                                                                            \
+  template hipError_t launch_moments<TF>(const double*, int, const double*, int, double, void*, hipStream_t); \
   template hipError_t launch_aggregate<TF>(const DevInc&, int, int, const void*, int, int, const void*, int,    \
-                                           double, double, int, int, int, void*, hipStream_t);              \
+                                           double, int, int, void*, hipStream_t);                           \
   template hipError_t launch_shift_up<TF>(const DevLevel&, const DevLevel&, const void*, void*, const void*,  \
                                           const void*, int, int, hipStream_t);                               \
   template hipError_t launch_shift_down<TF>(const DevLevel&, const void*, void*, const void*, const void*,   \
@@ -659,9 +668,9 @@ hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N,
                                             hipStream_t);
 INST_F(float)
 INST_F(double)
-template hipError_t launch_receive<float, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, double, const void*, int, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<double, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, double, const void*, int, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<float, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, double, const void*, int, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<double, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, double, const void*, int, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<float, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<double, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<float, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<double, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, void*, int, hipStream_t);
 
 }  // namespace pie

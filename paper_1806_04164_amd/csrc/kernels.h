@@ -18,12 +18,15 @@ hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, in
                             hipStream_t st);
 
 // far.hip
-size_t aggregate_smem(int maxpt, int Q, int nsplit, int RC, int tf_bytes);
-size_t receive_smem(int maxpt, int Q, int maxjoin, int RC, int tf_bytes);
+size_t aggregate_smem(int maxinc, int Q, int nsplit, int RC, int tf_bytes);
+size_t receive_smem(int maxinc, int Q, int maxjoin, int RC, int tf_bytes);
+// Per-incidence moment table M[ninc][Q][4] (M0, M1x, M1y, M1z) at the finest level.
 template <typename TF>
-hipError_t launch_aggregate(const DevInc& I, int nb, int maxpt, const void* x, int ldx, int R, const void* khat,
-                            int Q, double kappa, double w2e, int conjx, int nsplit, int phase_mode, void* S,
-                            hipStream_t st);
+hipError_t launch_moments(const double* pw, int ninc, const double* khat64, int Q, double kappa, void* M,
+                          hipStream_t st);
+template <typename TF>
+hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, int ldx, int R, const void* M,
+                            int Q, double w2e, int conjx, int nsplit, void* S, hipStream_t st);
 // Filter tables (Ft for the upward, F for the downward shift) carry SQT
 // trailing zeros.
 template <typename TF>
@@ -37,9 +40,9 @@ template <typename TF>
 hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, void* Gout, int Q, int R,
                             hipStream_t st);
 template <typename TF, typename TN>
-hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxpt, int maxjoin,
-                          const void* Gin, const void* khat, int Q, double kappa, const void* part, int R,
-                          int flags, int phase_mode, void* y, int ldy, hipStream_t st);
+hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxinc, int maxjoin,
+                          const void* Gin, const void* M, int Q, const void* part, int R, int flags, void* y,
+                          int ldy, hipStream_t st);
 template <typename TN>
 hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N, int R, int conjx, void* xb,
                              hipStream_t st);

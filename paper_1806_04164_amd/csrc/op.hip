@@ -35,11 +35,9 @@ struct pie_op {
   int near_prec = 64, far_prec = 64, tau = 0, nth = 0, nph = 0, Q = 0;
   double xs = 0;
   int max_rhs = 1, rc = 1, L = 0, N = 0, ne = 0, nt = 0;
-  int maxpt = 0;
+  int maxinc = 0;   // most (box, triangle) incidences of a finest box
   int maxjoin = 0;  // longest near-field join list of a finest box
-  int nsplit = 1;  // aggregation point-loop split (fixed per operator: RHS-batch-independent order)
-  int phase_mode = 0;  // pattern phases: 1 short Taylor, 2 long Taylor, 0 library sincos
-  double theta_max = 0.0;
+  int nsplit = 1;  // aggregation incidence-loop split (fixed per operator: RHS-batch-independent order)
   // device geometry
   double *dV = nullptr, *dP = nullptr, *dW = nullptr, *dC = nullptr, *dN = nullptr;
   int32_t* dT = nullptr;
@@ -60,6 +58,10 @@ struct pie_op {
   // needs only the finest patterns and overlaps the upward shifts
   hipStream_t side2 = nullptr;
   hipEvent_t ev_agg = nullptr, ev_il = nullptr;
+  // launch schedule (every choice gives the same result, bit for bit)
+  int sched_near = PIE_NEAR_FORK_START;  // where the near field forks off the far chain
+  int sched_il = 1;                      // finest translation on the third stream
+  int sched_chunk = 4;                   // widest RHS chunk (1, 2 or 4; at most rc)
   // incidences
   pie::DevInc I{};
   int64_t ninc = 0;
@@ -68,7 +70,7 @@ struct pie_op {
   std::vector<double> s_l, kappa_l, d_l;
   int64_t il_pairs = 0;
   // tables in far precision
-  void* dKhat = nullptr;
+  void* dM = nullptr;  // per-incidence moments [ninc][Q][4] in far precision
   std::vector<void*> dTl, dFl, dFtl, dPhl;
   // workspace
   std::vector<void*> dS, dG;
@@ -96,6 +98,15 @@ struct pie_op {
     }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+struct pie_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~pie_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
   }
 };
 
@@ -171,10 +182,8 @@ std::vector<TF> cast_vec(const std::vector<double>& v) {
 template <typename TF>
 pie_status upload_tables(pie_op* op, const std::vector<double>& khat, const std::vector<std::vector<double>>& T,
                          const std::vector<std::vector<double>>& F, const std::vector<std::vector<double>>& Ph) {
-  TF* p = nullptr;
-  pie_status s = upload(op, &p, cast_vec<TF>(khat));
-  if (s) return s;
-  op->dKhat = p;
+  pie_status s = PIE_OK;
+  (void)khat;
   op->dTl.assign(op->L + 1, nullptr);
   op->dFl.assign(op->L + 1, nullptr);
   op->dFtl.assign(op->L + 1, nullptr);
@@ -379,7 +388,7 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     maxinc = std::max(maxinc, iptr[b + 1] - iptr[b]);
   }
   op->ninc = (int64_t)itri.size();
-  op->maxpt = 7 * maxinc;
+  op->maxinc = maxinc;
   {
     // geometry relative to the finest box centre (the same centre formula
     // as the level tables below)
@@ -500,25 +509,6 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     op->lv[l] = dl;
     op->il_pairs += (int64_t)lvh.il_src.size();
   }
-  // ---------------- largest pattern phase |kappa_L khat.(r_i - C_box)| <= kappa_L |r_i - C_box|
-  {
-    const Level& fl2 = t.lev[L];
-    const double dL = op->d_l[L];
-    double rmax = 0.0;
-    for (int b = 0; b < nbL; ++b) {
-      double c[3];
-      for (int d = 0; d < 3; ++d) c[d] = t.origin[d] + ((double)fl2.coords[3 * b + d] + 0.5) * dL;
-      for (int j = iptr[b]; j < iptr[b + 1]; ++j)
-        for (int i = 0; i < 7; ++i) {
-          const double* pp = &P[21 * (size_t)itri[j] + 3 * i];
-          double dx = pp[0] - c[0], dy = pp[1] - c[1], dz = pp[2] - c[2];
-          rmax = std::max(rmax, std::sqrt(dx * dx + dy * dy + dz * dz));
-        }
-    }
-    op->theta_max = op->kappa_l[L] * rmax * (1.0 + 1e-12);
-    const double lim = op->far_prec == PIE_FP32 ? 0.2 : 0.1;
-    op->phase_mode = op->theta_max <= lim ? 1 : (op->theta_max <= 0.5 ? 2 : 0);
-  }
   // ---------------- k-space samples and tables (FP64)
   const int Q = op->Q, tau = op->tau;
   std::vector<double> ct, wt;
@@ -619,21 +609,25 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   op->rc = 0;
   for (int rc : {4, 2, 1}) {
     if (rc > op->max_rhs && rc > 1) continue;
-    size_t a = aggregate_smem(op->maxpt, Q, 1, rc, tfb);
-    size_t r = receive_smem(op->maxpt, Q, op->maxjoin, rc, tfb);
+    size_t a = aggregate_smem(op->maxinc, Q, 1, rc, tfb);
+    size_t r = receive_smem(op->maxinc, Q, op->maxjoin, rc, tfb);
     if (a <= 65536 && r <= 65536) {
       op->rc = rc;
       break;
     }
   }
   if (op->rc == 0) {
-    set_error("a finest box has too many quadrature points for the LDS budget; use more levels");
+    set_error("a finest box has too many incidences for the LDS budget; use more levels");
+    return PIE_ERR_UNSUPPORTED;
+  }
+  if (Q > 256) {
+    set_error("more than 256 k-space samples per level are not supported");
     return PIE_ERR_UNSUPPORTED;
   }
   {
     const int rcm = op->rc <= 1 ? 1 : (op->rc <= 2 ? 2 : 4);
     op->nsplit = 256 / Q < 1 ? 1 : 256 / Q;
-    while (op->nsplit > 1 && aggregate_smem(op->maxpt, Q, op->nsplit, rcm, tfb) > 65536) --op->nsplit;
+    while (op->nsplit > 1 && aggregate_smem(op->maxinc, Q, op->nsplit, rcm, tfb) > 65536) --op->nsplit;
   }
   // ---------------- workspace
   const size_t cxf = 2 * (size_t)tfb, cxn = op->near_prec == PIE_FP32 ? 8 : 16;
@@ -654,6 +648,17 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   if ((s = dalloc(op, &op->dKhR, 3 * (size_t)op->max_rhs)) || (s = dalloc(op, &op->dPolR, 3 * (size_t)op->max_rhs)) ||
       (s = dalloc(op, &op->dAmpR, 2 * (size_t)op->max_rhs)))
     return s;
+  // ---------------- finest-level moments of every incidence (FP64 phases)
+  {
+    unsigned char* mt;
+    double* dkh;
+    if ((s = dalloc(op, &mt, (size_t)op->ninc * Q * 4 * cxf)) || (s = upload(op, &dkh, khat))) return s;
+    op->dM = mt;
+    hipError_t em = op->far_prec == PIE_FP32
+                        ? launch_moments<float>(op->I.pw, (int)op->ninc, dkh, Q, op->kappa_l[L], mt, st)
+                        : launch_moments<double>(op->I.pw, (int)op->ninc, dkh, Q, op->kappa_l[L], mt, st);
+    if (em != hipSuccess) return hip_fail(em, "moments launch");
+  }
   // ---------------- near-field fill and diagonal (FP64 arithmetic)
   unsigned char* nz;
   if ((s = dalloc(op, &nz, (size_t)op->near_stored * cxn))) return s;
@@ -706,15 +711,16 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
   const int L = op->L, Q = op->Q;
   const bool near = flags & 1, far = flags & 2, adj = flags & 4;
   hipError_t e;
-  // The near field runs on the operator's side stream, overlapping the far
-  // field's chain on the caller's stream; reception joins the two.
-  const bool fork = near && far;
+  // The near field runs either before the far chain on the caller's stream
+  // or on the operator's side stream, forked at the start or after the
+  // aggregation and joined before the reception.
+  const bool fork = near && far && op->sched_near != PIE_NEAR_SERIAL;
   hipStream_t sn = fork ? op->side : st;
-  if (fork) {
-    HIPCHK(hipEventRecord(op->ev_fork, st), "fork");
-    HIPCHK(hipStreamWaitEvent(sn, op->ev_fork, 0), "fork");
-  }
-  if (near) {
+  auto near_field = [&]() -> pie_status {
+    if (fork) {
+      HIPCHK(hipEventRecord(op->ev_fork, st), "fork");
+      HIPCHK(hipStreamWaitEvent(sn, op->ev_fork, 0), "fork");
+    }
     if ((e = stage(op, PIE_STAGE_PERMUTE, sn, [&] {
            return launch_permute_in<TN>(x, ld, op->dPerm, op->N, R, adj, op->dXb, sn);
          })) != hipSuccess)
@@ -723,18 +729,28 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
            return launch_near_spmm<TN>(op->NB, op->dNear, op->dXb, R, op->dPart, R, sn);
          })) != hipSuccess)
       return hip_fail(e, "near spmm");
+    if (fork) HIPCHK(hipEventRecord(op->ev_join, sn), "join");
+    return PIE_OK;
+  };
+  const bool near_late = fork && op->sched_near == PIE_NEAR_FORK_AFTER_AGGREGATE;
+  if (near && !near_late) {
+    pie_status ps = near_field();
+    if (ps) return ps;
   }
-  if (fork) HIPCHK(hipEventRecord(op->ev_join, sn), "join");
   const DevBasis B = basis(op);
   if (far) {
     if ((e = stage(op, PIE_STAGE_AGGREGATE, st, [&] {
-           return launch_aggregate<TF>(op->I, op->lv[L].nb, op->maxpt, x, ld, R, op->dKhat, Q, op->kappa_l[L],
-                                       op->w2e, adj, op->nsplit, op->phase_mode, op->dS[L], st);
+           return launch_aggregate<TF>(op->I, op->lv[L].nb, op->maxinc, x, ld, R, op->dM, Q, op->w2e, adj,
+                                       op->nsplit, op->dS[L], st);
          })) != hipSuccess)
       return hip_fail(e, "aggregate");
+    if (near_late) {
+      pie_status ps = near_field();
+      if (ps) return ps;
+    }
     // finest-level translation on the third stream, concurrent with the
     // upward shifts and the coarser translations
-    const bool fork2 = L > 3;
+    const bool fork2 = L > 3 && op->sched_il;
     auto translate = [&](int l, hipStream_t s) {
       return stage(op, PIE_STAGE_TRANSLATE, s, [&] {
         return launch_translate<TF>(op->lv[l], op->dS[l], op->dTl[l], op->dG[l], Q, R, s);
@@ -767,9 +783,8 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
   int rflags = (near ? 1 : 0) | (far ? 2 : 0) | (adj ? 4 : 0);
   if (fork) HIPCHK(hipStreamWaitEvent(st, op->ev_join, 0), "join");
   if ((e = stage(op, PIE_STAGE_RECEIVE, st, [&] {
-         return launch_receive<TF, TN>(op->I, B, op->NB, op->lv[L].nb, op->maxpt, op->maxjoin, op->dG[L],
-                                       op->dKhat, Q, op->kappa_l[L], op->dPart, R, rflags, op->phase_mode, y,
-                                       ld, st);
+         return launch_receive<TF, TN>(op->I, B, op->NB, op->lv[L].nb, op->maxinc, op->maxjoin, op->dG[L],
+                                       op->dM, Q, op->dPart, R, rflags, y, ld, st);
        })) != hipSuccess)
     return hip_fail(e, "receive");
   return PIE_OK;
@@ -781,7 +796,8 @@ pie_status mvm(pie_op* op, const void* x, void* y, int64_t R, int flags, hipStre
   int64_t r0 = 0;
   while (r0 < R) {
     const int64_t rem = R - r0;
-    const int rw = (rem >= 4 && op->rc >= 4) ? 4 : ((rem >= 2 && op->rc >= 2) ? 2 : 1);
+    const int cap = std::min(op->rc, op->sched_chunk);
+    const int rw = (rem >= 4 && cap >= 4) ? 4 : ((rem >= 2 && cap >= 2) ? 2 : 1);
     const void* xc = (const cx<double>*)x + r0;
     void* yc = (cx<double>*)y + r0;
     pie_status s;
@@ -1068,6 +1084,131 @@ pie_status pie_matvec_far(pie_op* op, const void* x, void* y, int64_t R, void* s
   if (s) return s;
   return mvm(op, x, y, R, 2, (hipStream_t)stream);
 }
+
+pie_status pie_schedule_get(const pie_op* op, pie_schedule* out) {
+  if (!op || !out) {
+    pie::set_error("null operator or output");
+    return PIE_ERR_ARG;
+  }
+  *out = pie_schedule{1, op->sched_near, op->sched_il, op->sched_chunk};
+  return PIE_OK;
+}
+
+pie_status pie_schedule_set(pie_op* op, const pie_schedule* sch) {
+  if (!op || !sch || sch->version != 1) {
+    pie::set_error("null operator or schedule, or schedule version != 1");
+    return PIE_ERR_ARG;
+  }
+  if (sch->near_fork < PIE_NEAR_SERIAL || sch->near_fork > PIE_NEAR_FORK_AFTER_AGGREGATE ||
+      (sch->il_fork != 0 && sch->il_fork != 1) ||
+      (sch->max_chunk != 1 && sch->max_chunk != 2 && sch->max_chunk != 4)) {
+    pie::set_error("invalid schedule");
+    return PIE_ERR_ARG;
+  }
+  op->sched_near = sch->near_fork;
+  op->sched_il = sch->il_fork;
+  op->sched_chunk = sch->max_chunk;
+  return PIE_OK;
+}
+
+pie_status pie_autotune(pie_op* op, const void* x, void* y, int64_t R, int32_t reps, void* stream,
+                        pie_schedule* chosen, double* ms) {
+  pie_status s = check_op_call(op, x, y, R);
+  if (s) return s;
+  if (reps < 1 || op->prof) {
+    pie::set_error(reps < 1 ? "reps must be >= 1" : "stage profiling must be off while tuning");
+    return PIE_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0), "tuner event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    pie::set_error("tuner event");
+    return PIE_ERR_HIP;
+  }
+  pie_schedule best{1, op->sched_near, op->sched_il, op->sched_chunk};
+  double best_ms = 1e300;
+  s = PIE_OK;
+  for (int nf = PIE_NEAR_SERIAL; nf <= PIE_NEAR_FORK_AFTER_AGGREGATE && !s; ++nf)
+    for (int il = 0; il <= 1 && !s; ++il)
+      for (int ch : {4, 2, 1}) {
+        // chunk widths above R or above the operator's limit repeat a smaller one
+        if (ch > 1 && (ch > op->rc || ch > R)) continue;
+        op->sched_near = nf;
+        op->sched_il = il;
+        op->sched_chunk = ch;
+        if ((s = mvm(op, x, y, R, 3, st))) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { s = PIE_ERR_HIP; break; }
+        for (int i = 0; i < reps && !s; ++i) s = mvm(op, x, y, R, 3, st);
+        if (s) break;
+        float t = 0.0f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+          s = PIE_ERR_HIP;
+          break;
+        }
+        const double per = (double)t / reps;
+        if (per < best_ms) {
+          best_ms = per;
+          best = pie_schedule{1, nf, il, ch};
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  op->sched_near = best.near_fork;
+  op->sched_il = best.il_fork;
+  op->sched_chunk = best.max_chunk;
+  if (s) {
+    if (s == PIE_ERR_HIP) pie::set_error("tuner timing failed");
+    return s;
+  }
+  if (chosen) *chosen = best;
+  if (ms) *ms = best_ms;
+  return PIE_OK;
+}
+
+pie_status pie_graph_create(pie_op* op, const void* x, void* y, int64_t R, int32_t adjoint, pie_graph** out) {
+  if (!out) {
+    pie::set_error("null output handle");
+    return PIE_ERR_ARG;
+  }
+  *out = nullptr;
+  pie_status s = check_op_call(op, x, y, R);
+  if (s) return s;
+  if (op->prof) {
+    pie::set_error("stage profiling must be off while capturing");
+    return PIE_ERR_ARG;
+  }
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+  auto g = std::make_unique<pie_graph>();
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = mvm(op, x, y, R, 3 | (adjoint ? 4 : 0), cs);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &gr);
+    g->graph = gr;
+    if (!s && e2 != hipSuccess) e = e2;
+    if (!s && e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  }
+  (void)hipStreamDestroy(cs);
+  if (s) return s;
+  if (e != hipSuccess) return hip_fail(e, "graph capture");
+  *out = g.release();
+  return PIE_OK;
+}
+
+pie_status pie_graph_launch(pie_graph* g, void* stream) {
+  if (!g || !g->exec) {
+    pie::set_error("null graph");
+    return PIE_ERR_ARG;
+  }
+  HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
+  return PIE_OK;
+}
+
+void pie_graph_destroy(pie_graph* g) { delete g; }
 
 pie_status pie_profile_enable(pie_op* op, int32_t on) {
   if (!op) {

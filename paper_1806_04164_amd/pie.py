@@ -101,6 +101,27 @@ def _dev(t, N=None, R=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+class Graph:
+    """pie_graph: one captured MVM of an operator on fixed x and y tensors,
+    replayed with launch().  Keeps the operator and tensors alive."""
+
+    def __init__(self, op, x, y, adjoint=False):
+        R = op._R(x)
+        self.op, self.x, self.y = op, x, y
+        h = ctypes.c_void_p()
+        check(lib().pie_graph_create(op.h, _dev(x, op.N), _dev(y, op.N, R), R, int(adjoint), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        check(lib().pie_graph_launch(self.h, _stream(stream)))
+        return self.y
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().pie_graph_destroy(self.h)
+            self.h = None
+
+
 class Operator:
     """pie_op: the PIE operator (near field + MLFMA far field) on the GPU."""
 
@@ -144,6 +165,35 @@ class Operator:
 
     def _R(self, x):
         return 1 if x.dim() == 1 else x.shape[1]
+
+    @property
+    def schedule(self) -> dict:
+        sc = _lib.pie_schedule()
+        check(lib().pie_schedule_get(self.h, ctypes.byref(sc)))
+        return {"near_fork": sc.near_fork, "il_fork": sc.il_fork, "max_chunk": sc.max_chunk}
+
+    @schedule.setter
+    def schedule(self, d: dict):
+        cur = self.schedule
+        cur.update(d)
+        sc = _lib.pie_schedule(1, cur["near_fork"], cur["il_fork"], cur["max_chunk"])
+        check(lib().pie_schedule_set(self.h, ctypes.byref(sc)))
+
+    def autotune(self, x, y=None, reps=10, stream=None):
+        """Times every schedule on x (R = its columns), keeps the fastest;
+        returns (schedule dict, ms per MVM)."""
+        import torch
+        R = self._R(x)
+        if y is None:
+            y = torch.empty_like(x)
+        sc, ms = _lib.pie_schedule(), ctypes.c_double()
+        check(lib().pie_autotune(self.h, _dev(x, self.N), _dev(y, self.N, R), R, int(reps), _stream(stream),
+                                 ctypes.byref(sc), ctypes.byref(ms)))
+        return {"near_fork": sc.near_fork, "il_fork": sc.il_fork, "max_chunk": sc.max_chunk}, ms.value
+
+    def graph(self, x, y, adjoint=False):
+        """Captures y = Z x (fixed tensors) into a HIP graph; see Graph."""
+        return Graph(self, x, y, adjoint)
 
     def matvec(self, x, y=None, adjoint=False, stream=None):
         import torch

@@ -138,7 +138,9 @@ typedef struct pie_options {
   double x;          /* 0: default for far_prec                        */
   int32_t n_theta;   /* 0: tau + 1                                     */
   int32_t n_phi;     /* 0: 2 tau + 2                                   */
-  int32_t max_rhs;   /* workspace is sized for up to this many RHS (>=1) */
+  int32_t max_rhs;   /* calls take up to this many RHS (>= 1); the far-
+                        field workspace holds min(max_rhs, 64) columns,
+                        wider calls run in passes of 64 */
   int32_t reserved;  /* 0                                              */
 } pie_options;
 
@@ -216,8 +218,8 @@ pie_status pie_profile_read(pie_op* op, double* ms, int64_t* launches);
  *     after the finest-level aggregation.  The reception joins it.
  *   il_fork: 1 runs the finest level's interaction-list translation on a
  *     third stream, concurrent with the upward shifts.
- *   max_chunk: widest group of RHS columns per kernel pass (1, 2 or 4; the
- *     operator's own limit from its LDS budget applies).
+ *   max_chunk: widest register group of RHS columns inside a kernel (1, 2
+ *     or 4; the operator's own limit from its LDS budget applies).
  * Default: PIE_NEAR_FORK_START, il_fork 1, max_chunk 4. */
 #define PIE_NEAR_SERIAL 0
 #define PIE_NEAR_FORK_START 1

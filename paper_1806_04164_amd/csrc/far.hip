@@ -2,11 +2,13 @@
 // diagonal translation with the scaled plane waves of Eq. (4) and the
 // modified translation function of Eq. (5), disaggregation and reception.
 //
-// Pattern layout (outgoing S and incoming G of every level), box-major:
-//   P[(box * Q + q) * 5R + c * R + r],  c in {Jx, Jy, Jz, sigma, u},
-// u = div J + w^2 eps0 sigma, R = the RHS columns of the launch.  A box's
-// Q x 5R values are contiguous, so the translation's gather of one source
-// box by the Q sample lanes of a workgroup is a single contiguous run.
+// Pattern layout (outgoing S and incoming G of every level), box-major and
+// column-major within a box:
+//   P[((box * W + r) * Q + q) * 5 + c],  c in {Jx, Jy, Jz, sigma, u},
+// u = div J + w^2 eps0 sigma, W = the RHS columns of the pass.  For one
+// column a box's Q x 5 values are contiguous, so the translation's gather of
+// one source box by the Q sample lanes of a workgroup is a single
+// contiguous run for any W.
 #include <algorithm>
 
 #include "device.h"
@@ -58,14 +60,17 @@ __global__ void __launch_bounds__(128) k_moments(const double* __restrict__ pw, 
   }
 }
 
-// Workgroup = one finest box.  Stage 1: thread per (incidence, RHS) forms
-// the coefficients (a, -b, xp, cu) in LDS.  Stage 2: thread (g, q) adds the
-// incidences j = g (mod nsplit) in order, four incidences' moments in flight;
-// stage 3 adds the nsplit slices in a fixed order.
+// Workgroup = one finest box; the W right-hand-side columns are taken in
+// groups of RC.  Stage 1: thread per (incidence, column) forms the
+// coefficients (a, -b, xp, cu) in LDS.  Stage 2: thread (g, q) adds the
+// incidences j = g (mod nsplit) in order, four incidences' moments in flight
+// (the box's moments are re-read from L2 for later groups); stage 3 adds
+// the nsplit slices in a fixed order.  Each column's arithmetic is the same
+// for any W and RC.
 template <typename TF, int RC>
 __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<double>* __restrict__ x, int ldx,
                                                    const cx<TF>* __restrict__ M, int Q, double w2e, int conjx,
-                                                   int nsplit, cx<TF>* __restrict__ S) {
+                                                   int nsplit, int W, cx<TF>* __restrict__ S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_box(blockIdx.x, nbox);
   if (b < 0) return;
@@ -73,95 +78,101 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
   constexpr int ncol = 5 * RC;
   cx<TF>* cf = (cx<TF>*)smem;                      // [ni][6][RC]: a, -bx, -by, -bz, xp, cu
   cx<TF>* part = cf + (size_t)ni * 6 * RC;         // [nsplit - 1][Q][5][RC]
-  for (int e = threadIdx.x; e < ni * RC; e += blockDim.x) {
-    const int jl = e / RC, r = e - jl * RC;
-    const size_t j = (size_t)(j0 + jl);
-    int xc[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) xc[k] = I.xc[4 * j + k];
-    double sv[3], dv[3], pv[3][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      sv[k] = I.rs[3 * j + k];
-      dv[k] = I.rd[3 * j + k];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) pv[k][c] = I.pv[9 * j + 3 * k + c];
-    }
-    cx<double> xv[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      xv[k] = xc[k] >= 0 ? x[(size_t)xc[k] * ldx + r] : mk(0.0, 0.0);
-      if (conjx) xv[k].im = -xv[k].im;
-    }
-    cx<double> a = mk(0.0, 0.0), bb[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)}, cu = mk(0.0, 0.0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      a = a + sv[k] * xv[k];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) bb[c] = bb[c] + (sv[k] * pv[k][c]) * xv[k];
-      cu = cu + dv[k] * xv[k];
-    }
-    cu = cu + w2e * xv[3];
-    cx<TF>* o = cf + (size_t)jl * 6 * RC + r;
-    o[0] = mk((TF)a.re, (TF)a.im);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) o[(1 + c) * RC] = mk((TF)-bb[c].re, (TF)-bb[c].im);
-    o[4 * RC] = mk((TF)xv[3].re, (TF)xv[3].im);
-    o[5 * RC] = mk((TF)cu.re, (TF)cu.im);
-  }
-  __syncthreads();
-  const int gsz = Q;
-  const int g = threadIdx.x / gsz, q = threadIdx.x - g * gsz;
+  const int g = threadIdx.x / Q, q = threadIdx.x - g * Q;
   const bool act = g < nsplit;
-  cx<TF> acc[ncol];
+  for (int c0 = 0; c0 < W; c0 += RC) {
+    if (c0 > 0) __syncthreads();
+    for (int e = threadIdx.x; e < ni * RC; e += blockDim.x) {
+      const int jl = e / RC, r = e - jl * RC;
+      const size_t j = (size_t)(j0 + jl);
+      int xc[4];
 #pragma unroll
-  for (int c = 0; c < ncol; ++c) acc[c] = mk<TF>(0, 0);
-  if (act) {
-    constexpr int U = 4;
-    for (int jl = g; jl < ni; jl += U * nsplit) {
-      cx<TF> m[U][4];
+      for (int k = 0; k < 4; ++k) xc[k] = c0 + r < W ? I.xc[4 * j + k] : -1;
+      double sv[3], dv[3], pv[3][3];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int jj = jl + u * nsplit;
-        const cx<TF>* mp = M + ((size_t)(j0 + (jj < ni ? jj : jl)) * Q + q) * 4;
+      for (int k = 0; k < 3; ++k) {
+        sv[k] = I.rs[3 * j + k];
+        dv[k] = I.rd[3 * j + k];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) m[u][t] = mp[t];
+        for (int c = 0; c < 3; ++c) pv[k][c] = I.pv[9 * j + 3 * k + c];
       }
-      __builtin_amdgcn_sched_barrier(0);  // keep the incidences' loads in flight together
+      cx<double> xv[4];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int jj = jl + u * nsplit;
-        if (jj < ni) {
-          const cx<TF>* c6 = cf + (size_t)jj * 6 * RC;
+      for (int k = 0; k < 4; ++k) {
+        xv[k] = xc[k] >= 0 ? x[(size_t)xc[k] * ldx + c0 + r] : mk(0.0, 0.0);
+        if (conjx) xv[k].im = -xv[k].im;
+      }
+      cx<double> a = mk(0.0, 0.0), bb[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)}, cu = mk(0.0, 0.0);
 #pragma unroll
-          for (int r = 0; r < RC; ++r) {
+      for (int k = 0; k < 3; ++k) {
+        a = a + sv[k] * xv[k];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              cfma(acc[c * RC + r], c6[r], m[u][1 + c]);
-              cfma(acc[c * RC + r], c6[(1 + c) * RC + r], m[u][0]);
+        for (int c = 0; c < 3; ++c) bb[c] = bb[c] + (sv[k] * pv[k][c]) * xv[k];
+        cu = cu + dv[k] * xv[k];
+      }
+      cu = cu + w2e * xv[3];
+      cx<TF>* o = cf + (size_t)jl * 6 * RC + r;
+      o[0] = mk((TF)a.re, (TF)a.im);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o[(1 + c) * RC] = mk((TF)-bb[c].re, (TF)-bb[c].im);
+      o[4 * RC] = mk((TF)xv[3].re, (TF)xv[3].im);
+      o[5 * RC] = mk((TF)cu.re, (TF)cu.im);
+    }
+    __syncthreads();
+    cx<TF> acc[ncol];
+#pragma unroll
+    for (int c = 0; c < ncol; ++c) acc[c] = mk<TF>(0, 0);
+    if (act) {
+      constexpr int U = 4;
+      for (int jl = g; jl < ni; jl += U * nsplit) {
+        cx<TF> m[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int jj = jl + u * nsplit;
+          const cx<TF>* mp = M + ((size_t)(j0 + (jj < ni ? jj : jl)) * Q + q) * 4;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) m[u][t] = mp[t];
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the incidences' loads in flight together
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int jj = jl + u * nsplit;
+          if (jj < ni) {
+            const cx<TF>* c6 = cf + (size_t)jj * 6 * RC;
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                cfma(acc[c * RC + r], c6[r], m[u][1 + c]);
+                cfma(acc[c * RC + r], c6[(1 + c) * RC + r], m[u][0]);
+              }
+              cfma(acc[3 * RC + r], c6[4 * RC + r], m[u][0]);
+              cfma(acc[4 * RC + r], c6[5 * RC + r], m[u][0]);
             }
-            cfma(acc[3 * RC + r], c6[4 * RC + r], m[u][0]);
-            cfma(acc[4 * RC + r], c6[5 * RC + r], m[u][0]);
           }
         }
       }
-    }
-    if (g > 0) {
-      cx<TF>* pp = part + ((size_t)(g - 1) * Q + q) * ncol;
+      if (g > 0) {
+        cx<TF>* pp = part + ((size_t)(g - 1) * Q + q) * ncol;
 #pragma unroll
-      for (int c = 0; c < ncol; ++c) pp[c] = acc[c];
+        for (int c = 0; c < ncol; ++c) pp[c] = acc[c];
+      }
     }
-  }
-  __syncthreads();
-  if (act && g == 0) {
-    for (int h = 1; h < nsplit; ++h) {
-      const cx<TF>* pp = part + ((size_t)(h - 1) * Q + q) * ncol;
+    __syncthreads();
+    if (act && g == 0) {
+      for (int h = 1; h < nsplit; ++h) {
+        const cx<TF>* pp = part + ((size_t)(h - 1) * Q + q) * ncol;
 #pragma unroll
-      for (int c = 0; c < ncol; ++c) acc[c] = acc[c] + pp[c];
+        for (int c = 0; c < ncol; ++c) acc[c] = acc[c] + pp[c];
+      }
+#pragma unroll
+      for (int r = 0; r < RC; ++r)
+        if (c0 + r < W) {
+          cx<TF>* o = S + (((size_t)b * W + c0 + r) * Q + q) * 5;
+#pragma unroll
+          for (int k = 0; k < 5; ++k) o[k] = acc[k * RC + r];
+        }
     }
-    cx<TF>* o = S + ((size_t)b * Q + q) * ncol;
-#pragma unroll
-    for (int c = 0; c < ncol; ++c) o[c] = acc[c];
   }
 }
 
@@ -259,9 +270,8 @@ __global__ void __launch_bounds__(256) k_shift_up(DevLevel Lp, DevLevel Lc,
 #pragma unroll
   for (int i = 0; i < SQT; ++i) acc[i] = mk<TF>(0, 0);
   if (act) {
-    const int ncol = 5 * R;
-    const cx<TF>* s = Sc + (size_t)c * Q * ncol + k * R + r;
-    shift_mac(Fs, qa, qb, [&](int qq) { return s[(size_t)qq * ncol]; }, acc);
+    const cx<TF>* s = Sc + (((size_t)c * R + r) * Q) * 5 + k;
+    shift_mac(Fs, qa, qb, [&](int qq) { return s[(size_t)qq * 5]; }, acc);
   }
   if (sl > 0) {
 #pragma unroll
@@ -285,7 +295,7 @@ __global__ void __launch_bounds__(256) k_shift_up(DevLevel Lp, DevLevel Lc,
     const int p = p0 + pl;
     cx<TF> v = mk<TF>(0, 0);
     for (int ch = Lp.child_ptr[p]; ch < Lp.child_ptr[p + 1]; ++ch) v = v + part[((ch - c0) * 5 + kk) * SQT + i];
-    Sp[((size_t)p * Q + q0 + i) * 5 * R + kk * R + r] = v;
+    Sp[(((size_t)p * R + r) * Q + q0 + i) * 5 + kk] = v;
   }
 }
 
@@ -315,10 +325,9 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
 #pragma unroll
   for (int i = 0; i < SQT; ++i) acc[i] = mk<TF>(0, 0);
   if (act) {
-    const int ncol = 5 * R;
-    const cx<TF>* gp = Gp + (size_t)Lc.parent[c] * Q * ncol + k * R + r;
+    const cx<TF>* gp = Gp + (((size_t)Lc.parent[c] * R + r) * Q) * 5 + k;
     const cx<TF>* pc = ph + (size_t)Lc.octant[c] * Q;
-    shift_mac(Fs, qa, qb, [&](int qq) { return conj(pc[qq]) * gp[(size_t)qq * ncol]; }, acc);
+    shift_mac(Fs, qa, qb, [&](int qq) { return conj(pc[qq]) * gp[(size_t)qq * 5]; }, acc);
   }
   if (sl > 0) {
 #pragma unroll
@@ -329,11 +338,10 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
     for (int h = 1; h < SHIFT_SLICES; ++h)
 #pragma unroll
       for (int i = 0; i < SQT; ++i) acc[i] = acc[i] + part[((size_t)h * SHIFT_LANES + lane) * SQT + i];
-    const int ncol = 5 * R;
-    cx<TF>* o = Gc + ((size_t)c * Q + q0) * ncol + k * R + r;
+    cx<TF>* o = Gc + (((size_t)c * R + r) * Q + q0) * 5 + k;
 #pragma unroll
     for (int i = 0; i < SQT; ++i)
-      if (i < nq) o[(size_t)i * ncol] = o[(size_t)i * ncol] + acc[i];
+      if (i < nq) o[(size_t)i * 5] = o[(size_t)i * 5] + acc[i];
   }
 }
 
@@ -375,7 +383,7 @@ __global__ void __launch_bounds__(512) k_translate(DevLevel Lv, const cx<TF>* __
 #pragma unroll
     for (int k = 0; k < 5; ++k) acc[k] = mk<TF>(0, 0);
     if (act) {
-      const cx<TF>* Sq = S + (size_t)q * ncol + r;
+      const cx<TF>* Sq = S + ((size_t)r * Q + q) * 5;
       for (int kk = gsp; kk < nil; kk += U * nsplit) {
         cx<TF> tv[U], sv[U][5];
 #pragma unroll
@@ -385,7 +393,7 @@ __global__ void __launch_bounds__(512) k_translate(DevLevel Lv, const cx<TF>* __
           tv[u] = ok ? T[(size_t)ilo[e] * Q + q] : mk<TF>(0, 0);
           const cx<TF>* sp = Sq + (size_t)(ok ? ils[e] : 0) * n;
 #pragma unroll
-          for (int k = 0; k < 5; ++k) sv[u][k] = sp[k * R];
+          for (int k = 0; k < 5; ++k) sv[u][k] = sp[k];
         }
         __builtin_amdgcn_sched_barrier(0);  // keep the entries' loads in flight together
 #pragma unroll
@@ -406,9 +414,9 @@ __global__ void __launch_bounds__(512) k_translate(DevLevel Lv, const cx<TF>* __
 #pragma unroll
         for (int k = 0; k < 5; ++k) acc[k] = acc[k] + pp[k];
       }
-      cx<TF>* o = Gout + (size_t)b * n + (size_t)q * ncol + r;
+      cx<TF>* o = Gout + (size_t)b * n + ((size_t)r * Q + q) * 5;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) o[k * R] = acc[k];
+      for (int k = 0; k < 5; ++k) o[k] = acc[k];
     }
     __syncthreads();
   }
@@ -431,7 +439,7 @@ constexpr int RECV_SLICES = 4;
 template <typename TF, typename TN, int RC>
 __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear NB, int nbox,
                                                  const cx<TF>* __restrict__ Gin, const cx<TF>* __restrict__ M,
-                                                 int Q, const cx<TN>* __restrict__ part, int flags,
+                                                 int Q, const cx<TN>* __restrict__ part, int flags, int W,
                                                  cx<double>* __restrict__ y, int ldy) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_box(blockIdx.x, nbox);
@@ -447,104 +455,113 @@ __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear N
   const int nslot = do_near ? nrow + NB.col_ptr[b + 1] - NB.col_ptr[b] : 0;
   for (int e = threadIdx.x; e < nslot; e += blockDim.x)
     slots[e] = e < nrow ? NB.prow[NB.row_ptr[b] + e] : NB.pcol[NB.col_blk[NB.col_ptr[b] + e - nrow]];
-  if (do_far) {
-    const cx<TF>* g = Gin + (size_t)b * Q * ncol;
-    for (int e = threadIdx.x; e < Q * ncol; e += blockDim.x) Gs[e] = g[e];
-  }
-  __syncthreads();
-  if (do_far) {
-    const int qs = (Q + RECV_SLICES - 1) / RECV_SLICES;
-    for (int base = 0; base < ni * RECV_SLICES; base += blockDim.x) {
-      const int t = base + threadIdx.x;
-      const int jl = t / RECV_SLICES, sl = t - jl * RECV_SLICES;
-      const bool act = jl < ni;
-      cx<TF> acc[6 * RC];
-#pragma unroll
-      for (int c = 0; c < 6 * RC; ++c) acc[c] = mk<TF>(0, 0);
-      if (act) {
-        const int qa = sl * qs, qb = min(Q, qa + qs);
-        const cx<TF>* mp = M + ((size_t)(j0 + jl) * Q) * 4;
-        for (int q = qa; q < qb; ++q) {
-          cx<TF> m[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) m[k] = conj(mp[4 * (size_t)q + k]);
-          const cx<TF>* gq = Gs + (size_t)q * ncol;
-#pragma unroll
-          for (int r = 0; r < RC; ++r) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const cx<TF> gc = gq[c * RC + r];
-              cfma(acc[r], m[1 + c], gc);
-              cfma(acc[(1 + c) * RC + r], m[0], gc);
-            }
-            cfma(acc[4 * RC + r], m[0], gq[3 * RC + r]);
-            cfma(acc[5 * RC + r], m[0], gq[4 * RC + r]);
-          }
-        }
-      }
-      // (s0 + s1) + (s2 + s3) across the four lanes of an incidence
-#pragma unroll
-      for (int c = 0; c < 6 * RC; ++c) {
-        acc[c].re += __shfl_xor(acc[c].re, 1);
-        acc[c].im += __shfl_xor(acc[c].im, 1);
-        acc[c].re += __shfl_xor(acc[c].re, 2);
-        acc[c].im += __shfl_xor(acc[c].im, 2);
-      }
-      if (act && sl == 0) {
-#pragma unroll
-        for (int c = 0; c < 6 * RC; ++c) red[(size_t)jl * 6 * RC + c] = acc[c];
+  const int u0 = NB.box_ptr[b], nu = NB.box_ptr[b + 1] - u0;
+  for (int c0 = 0; c0 < W; c0 += RC) {
+    if (c0 > 0) __syncthreads();
+    if (do_far) {
+      for (int e = threadIdx.x; e < Q * ncol; e += blockDim.x) {
+        const int r = e / (5 * Q), qk = e - r * 5 * Q;   // source order: column, sample, component
+        const int q = qk / 5, k = qk - q * 5;
+        Gs[(size_t)q * ncol + k * RC + r] =
+            c0 + r < W ? Gin[(((size_t)b * W + c0 + r) * Q) * 5 + qk] : mk<TF>(0, 0);
       }
     }
     __syncthreads();
-  }
-  const int u0 = NB.box_ptr[b], nu = NB.box_ptr[b + 1] - u0;
-  for (int e = threadIdx.x; e < nu * RC; e += blockDim.x) {
-    const int ul = e / RC, r = e - ul * RC;
-    const int u = u0 + ul;
-    const int cu = B.perm[u];
-    cx<double> val = mk(0.0, 0.0);
     if (do_far) {
-      if (cu < B.ne) {
+      const int qs = (Q + RECV_SLICES - 1) / RECV_SLICES;
+      for (int base = 0; base < ni * RECV_SLICES; base += blockDim.x) {
+        const int t = base + threadIdx.x;
+        const int jl = t / RECV_SLICES, sl = t - jl * RECV_SLICES;
+        const bool act = jl < ni;
+        cx<TF> acc[6 * RC];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const cx<TF>* rv = red + (size_t)(I.uj[2 * u + h] - j0) * 6 * RC + r;
-          const double s = I.us[2 * u + h], d = I.ud[2 * u + h];
-          cx<double> t = mk((double)rv[0].re, (double)rv[0].im);
+        for (int c = 0; c < 6 * RC; ++c) acc[c] = mk<TF>(0, 0);
+        if (act) {
+          const int qa = sl * qs, qb = min(Q, qa + qs);
+          const cx<TF>* mp = M + ((size_t)(j0 + jl) * Q) * 4;
+          for (int q = qa; q < qb; ++q) {
+            cx<TF> m[4];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double pc = I.upv[6 * (size_t)u + 3 * h + c];
-            t.re -= pc * (double)rv[(1 + c) * RC].re;
-            t.im -= pc * (double)rv[(1 + c) * RC].im;
+            for (int k = 0; k < 4; ++k) m[k] = conj(mp[4 * (size_t)q + k]);
+            const cx<TF>* gq = Gs + (size_t)q * ncol;
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                const cx<TF> gc = gq[c * RC + r];
+                cfma(acc[r], m[1 + c], gc);
+                cfma(acc[(1 + c) * RC + r], m[0], gc);
+              }
+              cfma(acc[4 * RC + r], m[0], gq[3 * RC + r]);
+              cfma(acc[5 * RC + r], m[0], gq[4 * RC + r]);
+            }
           }
-          val.re += mu0 * s * t.re + d * (double)rv[4 * RC].re;
-          val.im += mu0 * s * t.im + d * (double)rv[4 * RC].im;
         }
-      } else {
-        const cx<TF>* rv = red + (size_t)(I.uj[2 * u] - j0) * 6 * RC + r;
-        val.re += (double)rv[5 * RC].re;
-        val.im += (double)rv[5 * RC].im;
-      }
-    }
-    if (do_near) {
-      int k = 0;
-      for (; k + 4 <= nslot; k += 4) {
-        cx<TN> v[4];
+        // (s0 + s1) + (s2 + s3) across the four lanes of an incidence
 #pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] = part[((size_t)slots[k + t] + ul) * RC + r];
+        for (int c = 0; c < 6 * RC; ++c) {
+          acc[c].re += __shfl_xor(acc[c].re, 1);
+          acc[c].im += __shfl_xor(acc[c].im, 1);
+          acc[c].re += __shfl_xor(acc[c].re, 2);
+          acc[c].im += __shfl_xor(acc[c].im, 2);
+        }
+        if (act && sl == 0) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          val.re += (double)v[t].re;
-          val.im += (double)v[t].im;
+          for (int c = 0; c < 6 * RC; ++c) red[(size_t)jl * 6 * RC + c] = acc[c];
         }
       }
-      for (; k < nslot; ++k) {
-        const cx<TN> v = part[((size_t)slots[k] + ul) * RC + r];
-        val.re += (double)v.re;
-        val.im += (double)v.im;
-      }
+      __syncthreads();
     }
-    if (conj_out) val.im = -val.im;
-    y[(size_t)cu * ldy + r] = val;
+    for (int e = threadIdx.x; e < nu * RC; e += blockDim.x) {
+      const int ul = e / RC, r = e - ul * RC;
+      if (c0 + r >= W) continue;
+      const int u = u0 + ul;
+      const int cu = B.perm[u];
+      cx<double> val = mk(0.0, 0.0);
+      if (do_far) {
+        if (cu < B.ne) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const cx<TF>* rv = red + (size_t)(I.uj[2 * u + h] - j0) * 6 * RC + r;
+            const double s = I.us[2 * u + h], d = I.ud[2 * u + h];
+            cx<double> t = mk((double)rv[0].re, (double)rv[0].im);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const double pc = I.upv[6 * (size_t)u + 3 * h + c];
+              t.re -= pc * (double)rv[(1 + c) * RC].re;
+              t.im -= pc * (double)rv[(1 + c) * RC].im;
+            }
+            val.re += mu0 * s * t.re + d * (double)rv[4 * RC].re;
+            val.im += mu0 * s * t.im + d * (double)rv[4 * RC].im;
+          }
+        } else {
+          const cx<TF>* rv = red + (size_t)(I.uj[2 * u] - j0) * 6 * RC + r;
+          val.re += (double)rv[5 * RC].re;
+          val.im += (double)rv[5 * RC].im;
+        }
+      }
+      if (do_near) {
+        const size_t col = (size_t)c0 + r;
+        int k = 0;
+        for (; k + 4 <= nslot; k += 4) {
+          cx<TN> v[4];
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) v[tt] = part[((size_t)slots[k + tt] + ul) * W + col];
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            val.re += (double)v[tt].re;
+            val.im += (double)v[tt].im;
+          }
+        }
+        for (; k < nslot; ++k) {
+          const cx<TN> v = part[((size_t)slots[k] + ul) * W + col];
+          val.re += (double)v.re;
+          val.im += (double)v.im;
+        }
+      }
+      if (conj_out) val.im = -val.im;
+      y[(size_t)cu * ldy + c0 + r] = val;
+    }
   }
 }
 
@@ -576,16 +593,19 @@ hipError_t launch_moments(const double* pw, int ninc, const double* khat64, int 
   return hipGetLastError();
 }
 
+// W columns per pass (x: [N][ldx] canonical, S: [box][Q][5][W]); rc: widest
+// register group (1, 2 or 4).
 template <typename TF>
-hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, int ldx, int R, const void* M,
-                            int Q, double w2e, int conjx, int nsplit, void* S, hipStream_t st) {
-  if (R != 1 && R != 2 && R != 4) return hipErrorInvalidValue;
+hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, int ldx, int W, int rc,
+                            const void* M, int Q, double w2e, int conjx, int nsplit, void* S, hipStream_t st) {
+  if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
   if (nsplit * Q > 256) return hipErrorInvalidValue;
+  const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
 #define AGG(RC_)                                                                                               \
   hipLaunchKernelGGL((k_aggregate<TF, RC_>), dim3(xcd_grid(nb)), dim3(256),                                    \
                      aggregate_smem(maxinc, Q, nsplit, RC_, sizeof(TF)), st, I, nb, (const cx<double>*)x, ldx, \
-                     (const cx<TF>*)M, Q, w2e, conjx, nsplit, (cx<TF>*)S)
-  if (R == 1) AGG(1); else if (R == 2) AGG(2); else AGG(4);
+                     (const cx<TF>*)M, Q, w2e, conjx, nsplit, W, (cx<TF>*)S)
+  if (g == 1) AGG(1); else if (g == 2) AGG(2); else AGG(4);
 #undef AGG
   return hipGetLastError();
 }
@@ -633,14 +653,15 @@ hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, vo
 
 template <typename TF, typename TN>
 hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxinc, int maxjoin,
-                          const void* Gin, const void* M, int Q, const void* part, int R, int flags, void* y,
-                          int ldy, hipStream_t st) {
-  if (R != 1 && R != 2 && R != 4) return hipErrorInvalidValue;
+                          const void* Gin, const void* M, int Q, const void* part, int W, int rc, int flags,
+                          void* y, int ldy, hipStream_t st) {
+  if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
+  const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
 #define REC(RC_)                                                                                            \
   hipLaunchKernelGGL((k_receive<TF, TN, RC_>), dim3(xcd_grid(nb)), dim3(256),                               \
                      receive_smem(maxinc, Q, maxjoin, RC_, sizeof(TF)), st, I, B, NB, nb, (const cx<TF>*)Gin, \
-                     (const cx<TF>*)M, Q, (const cx<TN>*)part, flags, (cx<double>*)y, ldy)
-  if (R == 1) REC(1); else if (R == 2) REC(2); else REC(4);
+                     (const cx<TF>*)M, Q, (const cx<TN>*)part, flags, W, (cx<double>*)y, ldy)
+  if (g == 1) REC(1); else if (g == 2) REC(2); else REC(4);
 #undef REC
   return hipGetLastError();
 }
@@ -656,8 +677,8 @@ hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N,
 
 #define INST_F(TF)                                                                                            \
   template hipError_t launch_moments<TF>(const double*, int, const double*, int, double, void*, hipStream_t); \
-  template hipError_t launch_aggregate<TF>(const DevInc&, int, int, const void*, int, int, const void*, int,    \
-                                           double, int, int, void*, hipStream_t);                           \
+  template hipError_t launch_aggregate<TF>(const DevInc&, int, int, const void*, int, int, int, const void*,   \
+                                           int, double, int, int, void*, hipStream_t);                      \
   template hipError_t launch_shift_up<TF>(const DevLevel&, const DevLevel&, const void*, void*, const void*,  \
                                           const void*, int, int, hipStream_t);                               \
   template hipError_t launch_shift_down<TF>(const DevLevel&, const void*, void*, const void*, const void*,   \
@@ -668,9 +689,9 @@ hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N,
                                             hipStream_t);
 INST_F(float)
 INST_F(double)
-template hipError_t launch_receive<float, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<double, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<float, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<double, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<float, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<double, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<float, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<double, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, int, void*, int, hipStream_t);
 
 }  // namespace pie

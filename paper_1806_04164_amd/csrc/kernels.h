@@ -13,8 +13,9 @@ hipError_t launch_near_fill(const DevGeo& G, const DevBasis& B, const DevNear& N
                             double w2e, hipStream_t st);
 hipError_t launch_diag(const DevGeo& G, const DevBasis& B, double* diag_abs, double k, double w2e,
                        hipStream_t st);
+// W right-hand-side columns per pass, register groups of at most rc columns.
 template <typename TN>
-hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part, int R,
+hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part, int W, int rc,
                             hipStream_t st);
 
 // far.hip
@@ -24,9 +25,10 @@ size_t receive_smem(int maxinc, int Q, int maxjoin, int RC, int tf_bytes);
 template <typename TF>
 hipError_t launch_moments(const double* pw, int ninc, const double* khat64, int Q, double kappa, void* M,
                           hipStream_t st);
+// W right-hand-side columns per pass, register groups of at most rc columns.
 template <typename TF>
-hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, int ldx, int R, const void* M,
-                            int Q, double w2e, int conjx, int nsplit, void* S, hipStream_t st);
+hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, int ldx, int W, int rc,
+                            const void* M, int Q, double w2e, int conjx, int nsplit, void* S, hipStream_t st);
 // Filter tables (Ft for the upward, F for the downward shift) carry SQT
 // trailing zeros.
 template <typename TF>
@@ -41,8 +43,8 @@ hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, vo
                             hipStream_t st);
 template <typename TF, typename TN>
 hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxinc, int maxjoin,
-                          const void* Gin, const void* M, int Q, const void* part, int R, int flags, void* y,
-                          int ldy, hipStream_t st);
+                          const void* Gin, const void* M, int Q, const void* part, int W, int rc, int flags,
+                          void* y, int ldy, hipStream_t st);
 template <typename TN>
 hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N, int R, int conjx, void* xb,
                              hipStream_t st);

@@ -228,15 +228,17 @@ __global__ void k_diag(DevGeo G, DevBasis B, double* diag_abs, double k, double 
 // transposed part c = Z_ab^T x_a (Z is symmetric) to a column slot.  Work
 // unit = one row panel of one block (at most 16 KiB of entries), so large
 // blocks spread over several workgroups and every workgroup streams one
-// 16-byte-vectorised panel into LDS; threads 0..127 then form its row sums
-// (one row each) and threads 128..255 its column sums (one column each, into
-// the panel's own column slot).  The reception kernel adds the slots in a
-// fixed order: no atomics, bitwise reproducible.
+// 16-byte-vectorised panel into LDS once; then, for each group of RC of the
+// W right-hand-side columns, threads 0..127 form its row sums (one row each)
+// and threads 128..255 its column sums (one column each, into the panel's
+// own column slot).  The reception kernel adds the slots in a fixed order:
+// no atomics, bitwise reproducible, and each column's arithmetic is the same
+// for any W and RC.
 // ---------------------------------------------------------------------------
 template <typename TN, int RC>
 __global__ void __launch_bounds__(256) k_near_spmm(DevNear NB, const cx<TN>* __restrict__ Z,
                                                    const cx<TN>* __restrict__ xb, int ldx,
-                                                   cx<TN>* __restrict__ part, int R) {
+                                                   cx<TN>* __restrict__ part, int W) {
   constexpr int ZCAP = sizeof(TN) == 4 ? 2048 : 1024;   // 16 KiB panel: 8 workgroups per CU
   constexpr int EPV = 16 / sizeof(cx<TN>);              // entries per 16-byte load
   __shared__ __align__(16) cx<TN> Zs[ZCAP];
@@ -260,42 +262,49 @@ __global__ void __launch_bounds__(256) k_near_spmm(DevNear NB, const cx<TN>* __r
     for (int e = tid; e < nv; e += blockDim.x) dst[e] = src[e];
     if (EPV == 2 && (cnt & 1) && tid == 0) Zs[cnt - 1] = src0[cnt - 1];
   }
-  if (tid < 128) {
-    if (tid < nb)
+  for (int c0 = 0; c0 < W; c0 += RC) {
+    if (c0 > 0) __syncthreads();  // the previous group's x staging is consumed
+    if (tid < 128) {
+      if (tid < nb)
 #pragma unroll
-      for (int r = 0; r < RC; ++r) xb_s[tid * RC + r] = xb[(size_t)(v0 + tid) * ldx + r];
-  } else if (offdiag && jc < nr) {
+        for (int r = 0; r < RC; ++r)
+          xb_s[tid * RC + r] = c0 + r < W ? xb[(size_t)(v0 + tid) * ldx + c0 + r] : mk<TN>(0, 0);
+    } else if (offdiag && jc < nr) {
 #pragma unroll
-    for (int r = 0; r < RC; ++r) xa_s[jc * RC + r] = xb[(size_t)(u0 + i0 + jc) * ldx + r];
-  }
-  __syncthreads();
-  if (tid < 128) {
-    if (tid < nr) {
-      cx<TN> racc[RC];
+      for (int r = 0; r < RC; ++r)
+        xa_s[jc * RC + r] = c0 + r < W ? xb[(size_t)(u0 + i0 + jc) * ldx + c0 + r] : mk<TN>(0, 0);
+    }
+    __syncthreads();
+    if (tid < 128) {
+      if (tid < nr) {
+        cx<TN> racc[RC];
 #pragma unroll
-      for (int r = 0; r < RC; ++r) racc[r] = mk<TN>(0, 0);
-      const cx<TN>* zr = Zs + (size_t)tid * nb;
-      for (int j = 0; j < nb; ++j) {
-        const cx<TN> z = zr[j];
+        for (int r = 0; r < RC; ++r) racc[r] = mk<TN>(0, 0);
+        const cx<TN>* zr = Zs + (size_t)tid * nb;
+        for (int j = 0; j < nb; ++j) {
+          const cx<TN> z = zr[j];
 #pragma unroll
-        for (int r = 0; r < RC; ++r) cfma(racc[r], z, xb_s[j * RC + r]);
+          for (int r = 0; r < RC; ++r) cfma(racc[r], z, xb_s[j * RC + r]);
+        }
+        cx<TN>* prow = part + ((size_t)NB.prow[blk] + i0 + tid) * W + c0;
+#pragma unroll
+        for (int r = 0; r < RC; ++r)
+          if (c0 + r < W) prow[r] = racc[r];
       }
-      cx<TN>* prow = part + ((size_t)NB.prow[blk] + i0 + tid) * R;
+    } else if (offdiag && jc < nb) {
+      cx<TN> cacc[RC];
 #pragma unroll
-      for (int r = 0; r < RC; ++r) prow[r] = racc[r];
+      for (int r = 0; r < RC; ++r) cacc[r] = mk<TN>(0, 0);
+      for (int i = 0; i < nr; ++i) {
+        const cx<TN> z = Zs[(size_t)i * nb + jc];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) cfma(cacc[r], z, xa_s[i * RC + r]);
+      }
+      cx<TN>* pcol = part + ((size_t)NB.pcol[task] + jc) * W + c0;
+#pragma unroll
+      for (int r = 0; r < RC; ++r)
+        if (c0 + r < W) pcol[r] = cacc[r];
     }
-  } else if (offdiag && jc < nb) {
-    cx<TN> cacc[RC];
-#pragma unroll
-    for (int r = 0; r < RC; ++r) cacc[r] = mk<TN>(0, 0);
-    for (int i = 0; i < nr; ++i) {
-      const cx<TN> z = Zs[(size_t)i * nb + jc];
-#pragma unroll
-      for (int r = 0; r < RC; ++r) cfma(cacc[r], z, xa_s[i * RC + r]);
-    }
-    cx<TN>* pcol = part + ((size_t)NB.pcol[task] + jc) * R;
-#pragma unroll
-    for (int r = 0; r < RC; ++r) pcol[r] = cacc[r];
   }
 }
 
@@ -323,26 +332,24 @@ hipError_t launch_diag(const DevGeo& G, const DevBasis& B, double* diag_abs, dou
   return hipGetLastError();
 }
 
+// W columns per pass (x: [N][ldx] box order, part: [slot][W]); rc: widest
+// register group (1, 2 or 4).
 template <typename TN>
-hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part, int R,
+hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part, int W, int rc,
                             hipStream_t st) {
   if (NB.ntask == 0) return hipSuccess;
-  if (R == 1)
-    hipLaunchKernelGGL((k_near_spmm<TN, 1>), dim3(NB.ntask), dim3(256), 0, st, NB, (const cx<TN>*)Z,
-                       (const cx<TN>*)xb, ldx, (cx<TN>*)part, R);
-  else if (R == 2)
-    hipLaunchKernelGGL((k_near_spmm<TN, 2>), dim3(NB.ntask), dim3(256), 0, st, NB, (const cx<TN>*)Z,
-                       (const cx<TN>*)xb, ldx, (cx<TN>*)part, R);
-  else if (R == 4)
-    hipLaunchKernelGGL((k_near_spmm<TN, 4>), dim3(NB.ntask), dim3(256), 0, st, NB, (const cx<TN>*)Z,
-                       (const cx<TN>*)xb, ldx, (cx<TN>*)part, R);
-  else
-    return hipErrorInvalidValue;
+  if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
+  const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
+#define NS(G_)                                                                                  \
+  hipLaunchKernelGGL((k_near_spmm<TN, G_>), dim3(NB.ntask), dim3(256), 0, st, NB, (const cx<TN>*)Z, \
+                     (const cx<TN>*)xb, ldx, (cx<TN>*)part, W)
+  if (g == 1) NS(1); else if (g == 2) NS(2); else NS(4);
+#undef NS
   return hipGetLastError();
 }
-template hipError_t launch_near_spmm<float>(const DevNear&, const void*, const void*, int, void*, int,
+template hipError_t launch_near_spmm<float>(const DevNear&, const void*, const void*, int, void*, int, int,
                                             hipStream_t);
-template hipError_t launch_near_spmm<double>(const DevNear&, const void*, const void*, int, void*, int,
+template hipError_t launch_near_spmm<double>(const DevNear&, const void*, const void*, int, void*, int, int,
                                              hipStream_t);
 
 }  // namespace pie

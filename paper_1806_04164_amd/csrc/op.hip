@@ -35,6 +35,7 @@ struct pie_op {
   int near_prec = 64, far_prec = 64, tau = 0, nth = 0, nph = 0, Q = 0;
   double xs = 0;
   int max_rhs = 1, rc = 1, L = 0, N = 0, ne = 0, nt = 0;
+  int pw = 1;  // RHS columns per MVM pass (workspace width): min(max_rhs, kPassMax)
   int maxinc = 0;   // most (box, triangle) incidences of a finest box
   int maxjoin = 0;  // longest near-field join list of a finest box
   int nsplit = 1;  // aggregation incidence-loop split (fixed per operator: RHS-batch-independent order)
@@ -100,6 +101,10 @@ struct pie_op {
     for (void* p : allocs) (void)hipFree(p);
   }
 };
+
+// Widest MVM pass: the far-field workspace holds this many RHS columns;
+// wider batches run in several passes.
+constexpr int kPassMax = 64;
 
 struct pie_graph {
   hipGraph_t graph = nullptr;
@@ -629,19 +634,20 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     op->nsplit = 256 / Q < 1 ? 1 : 256 / Q;
     while (op->nsplit > 1 && aggregate_smem(op->maxinc, Q, op->nsplit, rcm, tfb) > 65536) --op->nsplit;
   }
-  // ---------------- workspace
+  // ---------------- workspace (one pass of pw RHS columns)
+  op->pw = std::min(op->max_rhs, kPassMax);
   const size_t cxf = 2 * (size_t)tfb, cxn = op->near_prec == PIE_FP32 ? 8 : 16;
   op->dS.assign(L + 1, nullptr);
   op->dG.assign(L + 1, nullptr);
   for (int l = 3; l <= L; ++l) {
     unsigned char *a, *b;
-    size_t n = (size_t)op->lv[l].nb * Q * 5 * op->rc * cxf;
+    size_t n = (size_t)op->lv[l].nb * Q * 5 * op->pw * cxf;
     if ((s = dalloc(op, &a, n)) || (s = dalloc(op, &b, n))) return s;
     op->dS[l] = a;
     op->dG[l] = b;
   }
   unsigned char *part, *xb;
-  if ((s = dalloc(op, &part, (size_t)op->nslots * op->rc * cxn)) || (s = dalloc(op, &xb, (size_t)N * op->rc * cxn)))
+  if ((s = dalloc(op, &part, (size_t)op->nslots * op->pw * cxn)) || (s = dalloc(op, &xb, (size_t)N * op->pw * cxn)))
     return s;
   op->dPart = part;
   op->dXb = xb;
@@ -709,6 +715,7 @@ DevBasis basis(const pie_op* op) { return DevBasis{op->dPerm, op->dBtri, op->dBf
 template <typename TF, typename TN>
 pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flags, hipStream_t st) {
   const int L = op->L, Q = op->Q;
+  const int rcap = std::min(op->rc, op->sched_chunk);  // widest register group of columns
   const bool near = flags & 1, far = flags & 2, adj = flags & 4;
   hipError_t e;
   // The near field runs either before the far chain on the caller's stream
@@ -726,7 +733,7 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
          })) != hipSuccess)
       return hip_fail(e, "permute");
     if ((e = stage(op, PIE_STAGE_NEAR, sn, [&] {
-           return launch_near_spmm<TN>(op->NB, op->dNear, op->dXb, R, op->dPart, R, sn);
+           return launch_near_spmm<TN>(op->NB, op->dNear, op->dXb, R, op->dPart, R, rcap, sn);
          })) != hipSuccess)
       return hip_fail(e, "near spmm");
     if (fork) HIPCHK(hipEventRecord(op->ev_join, sn), "join");
@@ -740,8 +747,8 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
   const DevBasis B = basis(op);
   if (far) {
     if ((e = stage(op, PIE_STAGE_AGGREGATE, st, [&] {
-           return launch_aggregate<TF>(op->I, op->lv[L].nb, op->maxinc, x, ld, R, op->dM, Q, op->w2e, adj,
-                                       op->nsplit, op->dS[L], st);
+           return launch_aggregate<TF>(op->I, op->lv[L].nb, op->maxinc, x, ld, R, rcap, op->dM, Q, op->w2e,
+                                       adj, op->nsplit, op->dS[L], st);
          })) != hipSuccess)
       return hip_fail(e, "aggregate");
     if (near_late) {
@@ -784,33 +791,32 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
   if (fork) HIPCHK(hipStreamWaitEvent(st, op->ev_join, 0), "join");
   if ((e = stage(op, PIE_STAGE_RECEIVE, st, [&] {
          return launch_receive<TF, TN>(op->I, B, op->NB, op->lv[L].nb, op->maxinc, op->maxjoin, op->dG[L],
-                                       op->dM, Q, op->dPart, R, rflags, y, ld, st);
+                                       op->dM, Q, op->dPart, R, rcap, rflags, y, ld, st);
        })) != hipSuccess)
     return hip_fail(e, "receive");
   return PIE_OK;
 }
 
 pie_status mvm(pie_op* op, const void* x, void* y, int64_t R, int flags, hipStream_t st) {
-  // chunks of exactly 4, 2 or 1 right-hand sides (compile-time widths in
-  // the pattern kernels); each column's arithmetic is the same in any chunk
+  // passes of at most pw columns; inside a pass the kernels take the
+  // columns in register groups of 1, 2 or 4, and each column's arithmetic
+  // is the same for any pass width or grouping
   int64_t r0 = 0;
   while (r0 < R) {
-    const int64_t rem = R - r0;
-    const int cap = std::min(op->rc, op->sched_chunk);
-    const int rw = (rem >= 4 && cap >= 4) ? 4 : ((rem >= 2 && cap >= 2) ? 2 : 1);
+    const int w = (int)std::min<int64_t>(R - r0, op->pw);
     const void* xc = (const cx<double>*)x + r0;
     void* yc = (cx<double>*)y + r0;
     pie_status s;
     if (op->far_prec == PIE_FP32 && op->near_prec == PIE_FP32)
-      s = mvm_chunk<float, float>(op, xc, yc, (int)R, rw, flags, st);
+      s = mvm_chunk<float, float>(op, xc, yc, (int)R, w, flags, st);
     else if (op->far_prec == PIE_FP32)
-      s = mvm_chunk<float, double>(op, xc, yc, (int)R, rw, flags, st);
+      s = mvm_chunk<float, double>(op, xc, yc, (int)R, w, flags, st);
     else if (op->near_prec == PIE_FP32)
-      s = mvm_chunk<double, float>(op, xc, yc, (int)R, rw, flags, st);
+      s = mvm_chunk<double, float>(op, xc, yc, (int)R, w, flags, st);
     else
-      s = mvm_chunk<double, double>(op, xc, yc, (int)R, rw, flags, st);
+      s = mvm_chunk<double, double>(op, xc, yc, (int)R, w, flags, st);
     if (s) return s;
-    r0 += rw;
+    r0 += w;
   }
   return PIE_OK;
 }
@@ -1133,7 +1139,7 @@ pie_status pie_autotune(pie_op* op, const void* x, void* y, int64_t R, int32_t r
   for (int nf = PIE_NEAR_SERIAL; nf <= PIE_NEAR_FORK_AFTER_AGGREGATE && !s; ++nf)
     for (int il = 0; il <= 1 && !s; ++il)
       for (int ch : {4, 2, 1}) {
-        // chunk widths above R or above the operator's limit repeat a smaller one
+        // register groups wider than R or than the operator's limit repeat a narrower one
         if (ch > 1 && (ch > op->rc || ch > R)) continue;
         op->sched_near = nf;
         op->sched_il = il;

@@ -257,6 +257,16 @@ typedef struct pie_graph pie_graph;
 pie_status pie_graph_create(pie_op* op, const void* x, void* y, int64_t R,
                             int32_t adjoint, pie_graph** out);
 pie_status pie_graph_launch(pie_graph* g, void* stream);
+/* Uneven batch: one graph holding the MVMs of nobj distinct operators
+ * (objects of different sizes and frequencies, each with its own device x,
+ * y [N_i][R_i] and R_i), captured one after another (each with its own
+ * stream forks), so that one launch runs every object.  Each object's
+ * result equals its own pie_matvec bit for bit.  PIE_ERR_ARG for a
+ * repeated operator or an invalid per-object call. */
+pie_status pie_graph_create_batch(pie_op* const* ops, int32_t nobj,
+                                  const void* const* xs, void* const* ys,
+                                  const int64_t* Rs, int32_t adjoint,
+                                  pie_graph** out);
 void pie_graph_destroy(pie_graph* g);
 
 /* ---------------------------------------------------------------- RHS --

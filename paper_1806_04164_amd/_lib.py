@@ -45,7 +45,7 @@ EXPORTS = [
     "pie_rhs_planewave", "pie_solve_opts_default", "pie_solve", "pie_farfield",
     "pie_profile_enable", "pie_profile_read", "pie_farfield_adjoint",
     "pie_schedule_get", "pie_schedule_set", "pie_autotune",
-    "pie_graph_create", "pie_graph_launch", "pie_graph_destroy",
+    "pie_graph_create", "pie_graph_launch", "pie_graph_destroy", "pie_graph_create_batch",
 ]
 STAGES = ["permute", "near", "aggregate", "shift_up", "translate", "receive", "shift_down"]
 
@@ -118,6 +118,8 @@ def lib():
         "pie_graph_create": (I32, [P, P, P, I64, I32, ctypes.POINTER(P)]),
         "pie_graph_launch": (I32, [P, P]),
         "pie_graph_destroy": (None, [P]),
+        "pie_graph_create_batch": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(P), ctypes.POINTER(P),
+                                         pI64, I32, ctypes.POINTER(P)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -1205,6 +1205,48 @@ pie_status pie_graph_create(pie_op* op, const void* x, void* y, int64_t R, int32
   return PIE_OK;
 }
 
+pie_status pie_graph_create_batch(pie_op* const* ops, int32_t nobj, const void* const* xs, void* const* ys,
+                                  const int64_t* Rs, int32_t adjoint, pie_graph** out) {
+  if (!out || !ops || !xs || !ys || !Rs || nobj < 1) {
+    pie::set_error("null argument or empty batch");
+    return PIE_ERR_ARG;
+  }
+  *out = nullptr;
+  for (int i = 0; i < nobj; ++i) {
+    pie_status s = check_op_call(ops[i], xs[i], ys[i], Rs[i]);
+    if (s) return s;
+    if (ops[i]->prof) {
+      pie::set_error("stage profiling must be off while capturing");
+      return PIE_ERR_ARG;
+    }
+    for (int j = 0; j < i; ++j)
+      if (ops[j] == ops[i]) {
+        pie::set_error("an operator appears twice in the batch");
+        return PIE_ERR_ARG;
+      }
+  }
+  // the objects' MVMs are captured one after another on one private stream
+  // (each with its own side-stream forks and joins, as in pie_graph_create)
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+  auto g = std::make_unique<pie_graph>();
+  pie_status s = PIE_OK;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int i = 0; i < nobj && !s; ++i) s = mvm(ops[i], xs[i], ys[i], Rs[i], 3 | (adjoint ? 4 : 0), cs);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &gr);
+    g->graph = gr;
+    if (!s && e2 != hipSuccess) e = e2;
+    if (!s && e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  }
+  (void)hipStreamDestroy(cs);
+  if (s) return s;
+  if (e != hipSuccess) return hip_fail(e, "batch graph capture");
+  *out = g.release();
+  return PIE_OK;
+}
+
 pie_status pie_graph_launch(pie_graph* g, void* stream) {
   if (!g || !g->exec) {
     pie::set_error("null graph");

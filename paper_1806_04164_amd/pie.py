@@ -29,9 +29,11 @@ class Mesh:
                                     ctypes.byref(h)))
         self.h = h
 
-    def __del__(self):
+    def __del__(self, _destroy=lib().pie_mesh_destroy):
+        # the destroy function is bound at definition time: it stays callable
+        # while the interpreter tears modules down
         if getattr(self, "h", None):
-            lib().pie_mesh_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def sizes(self):
@@ -63,9 +65,11 @@ class Tree:
         check(lib().pie_tree_build(mesh.h, levels, ctypes.byref(h)))
         self.h = h
 
-    def __del__(self):
+    def __del__(self, _destroy=lib().pie_tree_destroy):
+        # the destroy function is bound at definition time: it stays callable
+        # while the interpreter tears modules down
         if getattr(self, "h", None):
-            lib().pie_tree_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def query(self, what: str, level: int = 0) -> np.ndarray:
@@ -116,9 +120,43 @@ class Graph:
         check(lib().pie_graph_launch(self.h, _stream(stream)))
         return self.y
 
-    def __del__(self):
+    def __del__(self, _destroy=lib().pie_graph_destroy):
+        # the destroy function is bound at definition time: it stays callable
+        # while the interpreter tears modules down
         if getattr(self, "h", None):
-            lib().pie_graph_destroy(self.h)
+            _destroy(self.h)
+            self.h = None
+
+
+class BatchGraph:
+    """pie_graph of an uneven batch: the MVMs y_i = Z_i x_i of several
+    distinct operators captured one after another into one graph; launch()
+    runs them all.  Keeps the operators and tensors alive."""
+
+    def __init__(self, ops, xs, ys, adjoint=False):
+        n = len(ops)
+        if not (n == len(xs) == len(ys)) or n == 0:
+            raise ValueError("ops, xs and ys must have the same non-zero length")
+        self.ops, self.xs, self.ys = list(ops), list(xs), list(ys)
+        P = ctypes.c_void_p
+        Rs = [op._R(x) for op, x in zip(ops, xs)]
+        hops = (P * n)(*[op.h.value for op in ops])
+        hx = (P * n)(*[_dev(x, op.N).value for op, x in zip(ops, xs)])
+        hy = (P * n)(*[_dev(y, op.N, R).value for op, y, R in zip(ops, ys, Rs)])
+        hr = (ctypes.c_int64 * n)(*Rs)
+        h = P()
+        check(lib().pie_graph_create_batch(hops, n, hx, hy, hr, int(adjoint), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        check(lib().pie_graph_launch(self.h, _stream(stream)))
+        return self.ys
+
+    def __del__(self, _destroy=lib().pie_graph_destroy):
+        # the destroy function is bound at definition time: it stays callable
+        # while the interpreter tears modules down
+        if getattr(self, "h", None):
+            _destroy(self.h)
             self.h = None
 
 
@@ -139,9 +177,11 @@ class Operator:
         self.N = self.info("N")
         self.max_rhs = max_rhs
 
-    def __del__(self):
+    def __del__(self, _destroy=lib().pie_operator_destroy):
+        # the destroy function is bound at definition time: it stays callable
+        # while the interpreter tears modules down
         if getattr(self, "h", None):
-            lib().pie_operator_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def info(self, what: str) -> int:

@@ -7,7 +7,7 @@ right-hand sides, inputs resident in HBM.  Metric: unknowns x RHS per second
 of the operator whose error against the FP64 dense oracle is <= 1e-3 per
 sub-operator (rows J/A x columns J/A), measured on sampled rows in the same
 run.  Precision modes:
-  mixed: near field FP32, far field FP64 (tau = 6, x = 0.07)  -> headline
+  mixed: near field FP32, far field FP64 (tau = 7, x = 0.05)  -> headline
   fp32:  near and far field FP32 (tau = 4, x = 0.15)
   fp64:  near and far field FP64, the plain FP64 single-RHS path (baseline)
 

@@ -123,8 +123,9 @@ pie_status pie_tree_query(const pie_tree* t, int32_t what, int32_t level,
  * number tau and scale factor s per box size in a reference that is not
  * reproduced; here s_l = min(1, k d_l / x) per level, so that the scaled box
  * size k d_l / s_l equals x wherever s < 1, and (tau, x) default per far
- * precision to values chosen by measured error against the dense matrix:
- *   far FP64: tau = 6, x = 0.07;  far FP32: tau = 4, x = 0.15.
+ * precision to values chosen by measured error against the dense matrix
+ * (sampled rows, 5 to 8 levels):
+ *   far FP64: tau = 7, x = 0.05 (Q = 128);  far FP32: tau = 4, x = 0.15.
  * k-space samples: n_theta Gauss-Legendre points in cos(theta) (default
  * tau+1) times n_phi uniform phi (default 2 tau + 2).
  * near_prec: storage and arithmetic of the near-field SpMM.

@@ -992,8 +992,8 @@ pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq
   op->near_prec = opt->near_prec;
   op->far_prec = opt->far_prec;
   const bool f32 = opt->far_prec == PIE_FP32;
-  op->tau = opt->tau > 0 ? opt->tau : (f32 ? 4 : 6);
-  op->xs = opt->x > 0.0 ? opt->x : (f32 ? 0.15 : 0.07);
+  op->tau = opt->tau > 0 ? opt->tau : (f32 ? 4 : 7);
+  op->xs = opt->x > 0.0 ? opt->x : (f32 ? 0.15 : 0.05);
   op->nth = opt->n_theta > 0 ? opt->n_theta : op->tau + 1;
   op->nph = opt->n_phi > 0 ? opt->n_phi : 2 * op->tau + 2;
   op->Q = op->nth * op->nph;

@@ -6,8 +6,10 @@ Tolerances and where they come from:
 * far field, FP64, tau=4, x=0.15: 1e-9.  The sampled translation amplifies
   round-off by about (2 tau + 1)!!/(2x)^tau = 1.2e5, so FP64 differences of
   order 1e-16 * 1.2e5 ~ 1e-11 are expected.
-* far field, FP64, tau=6, x=0.07 (the FP64 default): amplification 1.8e10,
-  so 1e-5.
+* far field, FP64, tau=6, x=0.07: amplification 1.8e10, so 1e-5.
+* far field, FP64, tau=7, x=0.05 (the FP64 default): amplification bound
+  15!!/0.1^7 = 2e13, i.e. at most ~2e-3 from FP64 rounding; held to that
+  bound (the realised difference is printed).
 * far field, FP32, tau=4, x=0.15: amplification about 1e5 times FP32
   rounding 6e-8 gives ~6e-3, and the charge of an RWG current nearly cancels
   (the divergence pattern is a dipole), which costs another factor of a few
@@ -88,6 +90,7 @@ def test_near_field(c1, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tau,xs,tol", [(PIE_FP64, 4, 0.15, 1e-9), (PIE_FP64, 6, 0.07, 1e-5),
+                                              (PIE_FP64, 7, 0.05, 2e-3),
                                              (PIE_FP32, 4, 0.15, 3e-2)])
 def test_far_field_single_level(c1, prec, tau, xs, tol):
     op = _op(c1, far=prec, tau=tau, x=xs)
@@ -173,11 +176,14 @@ def test_solve_against_lu_and_mie(c1, c1_dense):
     """GMRES on the GPU operator against the dense LU solution.  The far
     field (the physical output) must agree to 1e-3; the current itself
     differs by cond(DZD) ~ 150 times the operator error (~3.5e-4 at the FP64
-    default), which the oracle's own MLFMA reproduces (4.6e-3), so 1e-2."""
+    default), which the oracle's own MLFMA reproduces (4.6e-3), so 1e-2.
+    Tolerance 1e-7: with tau = 7, x = 0.05 the translation amplifies FP64
+    rounding enough that the floating-point MVM is linear only to ~1e-8, the
+    floor of any Krylov residual."""
     op = _op(c1)
     prob = c1["prob"]
     b = op.rhs_planewave(*synth.axial_wave())
-    x, info = op.solve(b, tol=1e-8, restart=200, maxit=3000)
+    x, info = op.solve(b, tol=1e-7, restart=200, maxit=3000)
     print("solve", info, flush=True)
     assert info["converged"]
     xs = host(x)[:, 0]
@@ -246,7 +252,7 @@ def test_fp64_residual_refinement(c1):
     x, info = fast.solve(b, res_op=ref, tol=1e-6, inner_tol=1e-3, refine=40, restart=200, maxit=4000)
     print("refinement", info, flush=True)
     assert info["converged"] and info["rel_residual"] <= 1e-6
-    x64, info64 = ref.solve(b, tol=1e-9, restart=200, maxit=4000)
+    x64, info64 = ref.solve(b, tol=1e-7, restart=200, maxit=4000)
     E = c1["E"]
     th = np.linspace(0, np.pi, 19)
     dirs = np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
@@ -261,7 +267,7 @@ def test_gradient_of_farfield_loss():
     (1) Against central finite differences on Re and Im: L is quadratic, so
     central differences are exact for any step up to the noise of L.  A step
     of 1e-6 moves L by only ~4e-6 relative, below what the iterative solves
-    resolve (their residual floor, and at the FP64 default tau = 6 the MVM's
+    resolve (their residual floor, and at the FP64 defaults the MVM's
     own ~1e-6 round-off noise), so the asserted check uses a step of 1e-2
     on an FP64 operator with tau = 4, x = 0.15 (round-off ~1e-11); the
     step-1e-6 differences are printed for reference.

@@ -123,6 +123,26 @@ def cpu_baseline_leg(w, x, rows):
     return dt, ref, E
 
 
+def near_traffic(workload):
+    """HBM bytes per near-field SpMM launch from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or
+    None if there is none for this workload or the kernel source changed
+    since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_mvm_kernels_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("near_spmm_traffic_bytes", "near_spmm_source_sha256"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    src = open(os.path.join(ROOT, "paper_1806_04164_amd", "csrc", "near.hip"), "rb").read()
+    if vals.get("near_spmm_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return float(vals["near_spmm_traffic_bytes"])
+
+
 def errors(y_of, ref, rows, E):
     out = {}
     for name in ("J", "A"):
@@ -140,6 +160,10 @@ def main():
     ap.add_argument("--workload", default="sphere_s5_1e-3lam_jit")
     ap.add_argument("--rows", type=int, default=48, help="sampled oracle rows for the accuracy gate")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (no accuracy gate)")
+    ap.add_argument("--modes", default="mixed,fp32,fp64", help="comma-separated precision modes to run")
+    ap.add_argument("--rhs", type=int, default=0, help="override the workload's number of right-hand sides")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB device-to-device 5 times (hardware-counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a "
@@ -150,8 +174,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     w = synth.WORKLOADS[args.workload]
-    R = w.nrhs
-    modes = ["mixed", "fp32", "fp64"]
+    R = args.rhs if args.rhs > 0 else w.nrhs
+    modes = [m for m in args.modes.split(",") if m]
+    if "mixed" not in modes:
+        print("the headline mode 'mixed' must be among --modes", file=sys.stderr)
+        sys.exit(2)
     mesh, tree, ops = build_ops(w, modes, R)
     N = ops["mixed"].N
     xh = synth.complex_gaussian(N, R, 1)
@@ -194,13 +221,15 @@ def main():
     st = res[head]["stages"]
     dom = max(st, key=lambda k: st[k][0])
     near_bytes = op.info("NEAR_BYTES") + 2 * N * R * 8
-    per_launch_ms = st["near"][0] / max(1, st["near"][1])
-    roof = dict(bound="hbm", kernel="near_spmm", achieved=near_bytes / (per_launch_ms * 1e-3) / 1e9,
-                peak=HBM_PEAK_GBS, unit="GB/s", traffic=None,
-                bytes_per_launch=near_bytes, ms_per_launch=per_launch_ms,
-                standalone_ms_per_launch=res[head]["near_alone_ms"],
-                standalone_frac=near_bytes / (res[head]["near_alone_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    in_mvm_ms = st["near"][0] / max(1, st["near"][1])
+    alone_ms = res[head]["near_alone_ms"]
+    roof = dict(bound="hbm", kernel="k_near_spmm (FP32 near field)",
+                achieved=near_bytes / (alone_ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                traffic=near_traffic(w.name), bytes_per_launch=near_bytes, ms_per_launch=alone_ms,
+                in_mvm_ms_per_launch=in_mvm_ms,
+                in_mvm_achieved=near_bytes / (in_mvm_ms * 1e-3) / 1e9)
     roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["in_mvm_frac"] = roof["in_mvm_achieved"] / roof["peak"]
     out = {
         "metric": "MLFMA matvec unknown*RHS/s at <=1e-3 rel err; batched FP32 vs plain FP64",
         "value": N * R / (res[head]["ms"] * 1e-3),
@@ -210,7 +239,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64 near / c128 far",
         "data": "synthetic",
-        "config": {"workload": w.name, "unknowns": N, "rhs": R, "levels": w.levels,
+        "config": {"workload": w.name if R == w.nrhs else f"{w.name} with {R} RHS", "unknowns": N, "rhs": R,
+                   "levels": w.levels,
                    "d_over_lambda": w.d_over_lambda, "subdivisions": w.subdiv,
                    "mode": head, "gate_passed": gate[head]},
         "roofline": roof,
@@ -223,9 +253,17 @@ def main():
                       "near_standalone_ms": res[m]["near_alone_ms"],
                       "stage_ms_per_launch": {k: v[0] / max(1, v[1]) for k, v in res[m]["stages"].items()}}
                   for m in modes},
-        "speedup_vs_fp64": res["fp64"]["ms"] / res[head]["ms"],
+        "speedup_vs_fp64": (res["fp64"]["ms"] / res[head]["ms"]) if "fp64" in res else None,
     }
     print(json.dumps(out), flush=True)
+    if args.copy_calibrate > 0:
+        n = args.copy_calibrate * (1 << 20) // 16
+        a = torch.zeros(n, dtype=torch.complex128, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 5 x {args.copy_calibrate} MiB device-to-device")
 
 
 if __name__ == "__main__":

@@ -186,10 +186,12 @@ def main():
     res = {}
     for m in modes:
         y = torch.empty_like(x)
-        ms, ms_eager, sched, stages = time_mvm(ops[m], x, y, args.steps, args.warmup)
-        res[m] = dict(ms=ms, ms_eager=ms_eager, schedule=sched, stages=stages,
+        ms_graph, ms_eager, sched, stages = time_mvm(ops[m], x, y, args.steps, args.warmup)
+        ms = min(ms_graph, ms_eager)
+        res[m] = dict(ms=ms, ms_graph=ms_graph, ms_eager=ms_eager,
+                      launch="graph" if ms_graph <= ms_eager else "eager", schedule=sched, stages=stages,
                       near_alone_ms=time_near_only(ops[m], x, y, args.steps))
-        log(f"[bench] {m}: {ms:.4f} ms/MVM (graph), {ms_eager:.4f} eager, schedule {sched}; stages(ms/launch) " +
+        log(f"[bench] {m}: {ms_graph:.4f} ms/MVM (graph), {ms_eager:.4f} eager, schedule {sched}; stages(ms/launch) " +
             " ".join(f"{k}={v[0] / max(1, v[1]):.4f}" for k, v in stages.items() if v[1]) +
             f"  near alone {res[m]['near_alone_ms']:.4f}")
     # --- accuracy gate on sampled rows (the oracle leg provides the reference)
@@ -242,11 +244,13 @@ def main():
         "config": {"workload": w.name if R == w.nrhs else f"{w.name} with {R} RHS", "unknowns": N, "rhs": R,
                    "levels": w.levels,
                    "d_over_lambda": w.d_over_lambda, "subdivisions": w.subdiv,
-                   "mode": head, "gate_passed": gate[head]},
+                   "mode": head, "launch": res[head]["launch"], "schedule": res[head]["schedule"],
+                   "gate_passed": gate[head]},
         "roofline": roof,
         "dominant_stage": dom,
         "cpu_baseline": cpu,
-        "modes": {m: {"ms_per_mvm": res[m]["ms"], "ms_per_mvm_eager": res[m]["ms_eager"],
+        "modes": {m: {"ms_per_mvm": res[m]["ms"], "launch": res[m]["launch"], "ms_per_mvm_graph": res[m]["ms_graph"],
+                      "ms_per_mvm_eager": res[m]["ms_eager"],
                       "schedule": res[m]["schedule"], "unknown_rhs_per_s": N * R / (res[m]["ms"] * 1e-3),
                       "max_block_err": (max(res[m]["err"].values()) if "err" in res[m] else None),
                       "gate_1e-3": gate[m],

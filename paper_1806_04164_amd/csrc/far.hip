@@ -22,6 +22,9 @@ namespace pie {
 // o_i = r_i - C_box, the moment table holds (set-up, FP64 phases)
 //   M0_j(q) = sum_i W_i e_i(q),   M1_j(q) = sum_i W_i o_i e_i(q),
 //   e_i(q) = exp(-i kappa khat_q . o_i).
+// The sample set is symmetric under khat -> -khat with the antipode of every
+// sample q >= Qh among the first Qh, so M(q) = conj M(anti[q]) and only the
+// first Qh samples are stored (Qh = Q/2; Qh = Q with anti[q] = q otherwise).
 // An RWG half s (r - p) on the triangle radiates s (M1 - (p - C) M0), its
 // divergence d M0 and a pulse M0, so with the incidence coefficients
 //   a = sum_k x_k s_k,  b = sum_k x_k s_k (p_k - C),  xp = x_pulse,
@@ -31,7 +34,7 @@ namespace pie {
 // ---------------------------------------------------------------------------
 template <typename TF>
 __global__ void __launch_bounds__(128) k_moments(const double* __restrict__ pw, const double* __restrict__ khat,
-                                                 int Q, double kappa, cx<TF>* __restrict__ M) {
+                                                 int Qh, double kappa, cx<TF>* __restrict__ M) {
   const int j = blockIdx.x;
   const double* p = pw + 28 * (size_t)j;
   double o[7][3], w[7];
@@ -41,7 +44,7 @@ __global__ void __launch_bounds__(128) k_moments(const double* __restrict__ pw, 
     for (int c = 0; c < 3; ++c) o[i][c] = p[4 * i + c];
     w[i] = p[4 * i + 3];
   }
-  for (int q = threadIdx.x; q < Q; q += blockDim.x) {
+  for (int q = threadIdx.x; q < Qh; q += blockDim.x) {
     const double kx = kappa * khat[3 * q], ky = kappa * khat[3 * q + 1], kz = kappa * khat[3 * q + 2];
     cx<double> m0 = mk(0.0, 0.0), m1[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
 #pragma unroll
@@ -53,7 +56,7 @@ __global__ void __launch_bounds__(128) k_moments(const double* __restrict__ pw, 
 #pragma unroll
       for (int c = 0; c < 3; ++c) m1[c] = m1[c] + o[i][c] * e;
     }
-    cx<TF>* out = M + ((size_t)j * Q + q) * 4;
+    cx<TF>* out = M + ((size_t)j * Qh + q) * 4;
     out[0] = mk((TF)m0.re, (TF)m0.im);
 #pragma unroll
     for (int c = 0; c < 3; ++c) out[1 + c] = mk((TF)m1[c].re, (TF)m1[c].im);
@@ -69,8 +72,9 @@ __global__ void __launch_bounds__(128) k_moments(const double* __restrict__ pw, 
 // for any W and RC.
 template <typename TF, int RC>
 __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<double>* __restrict__ x, int ldx,
-                                                   const cx<TF>* __restrict__ M, int Q, double w2e, int conjx,
-                                                   int nsplit, int W, cx<TF>* __restrict__ S) {
+                                                   const cx<TF>* __restrict__ M, const int32_t* __restrict__ anti,
+                                                   int Q, int Qh, double w2e, int conjx, int nsplit, int W,
+                                                   cx<TF>* __restrict__ S) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_box(blockIdx.x, nbox);
   if (b < 0) return;
@@ -80,6 +84,8 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
   cx<TF>* part = cf + (size_t)ni * 6 * RC;         // [nsplit - 1][Q][5][RC]
   const int g = threadIdx.x / Q, q = threadIdx.x - g * Q;
   const bool act = g < nsplit;
+  const int qm = act ? anti[q] : 0;      // stored sample of q
+  const bool cjm = q >= Qh;              // M(q) = conj M(qm)
   for (int c0 = 0; c0 < W; c0 += RC) {
     if (c0 > 0) __syncthreads();
     for (int e = threadIdx.x; e < ni * RC; e += blockDim.x) {
@@ -129,9 +135,9 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int jj = jl + u * nsplit;
-          const cx<TF>* mp = M + ((size_t)(j0 + (jj < ni ? jj : jl)) * Q + q) * 4;
+          const cx<TF>* mp = M + ((size_t)(j0 + (jj < ni ? jj : jl)) * Qh + qm) * 4;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) m[u][t] = mp[t];
+          for (int t = 0; t < 4; ++t) m[u][t] = cjm ? conj(mp[t]) : mp[t];
         }
         __builtin_amdgcn_sched_barrier(0);  // keep the incidences' loads in flight together
 #pragma unroll
@@ -439,7 +445,8 @@ constexpr int RECV_SLICES = 4;
 template <typename TF, typename TN, int RC>
 __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear NB, int nbox,
                                                  const cx<TF>* __restrict__ Gin, const cx<TF>* __restrict__ M,
-                                                 int Q, const cx<TN>* __restrict__ part, int flags, int W,
+                                                 const int32_t* __restrict__ anti, int Q, int Qh,
+                                                 const cx<TN>* __restrict__ part, int flags, int W,
                                                  cx<double>* __restrict__ y, int ldy) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_box(blockIdx.x, nbox);
@@ -449,12 +456,15 @@ __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear N
   const bool do_far = flags & 2, do_near = flags & 1, conj_out = flags & 4;
   cx<TF>* Gs = (cx<TF>*)smem;                              // [Q][5][RC]
   cx<TF>* red = Gs + (size_t)Q * ncol;                     // [ni][6][RC]: A, Bx, By, Bz, Cs, Du
-  int32_t* slots = (int32_t*)(red + (size_t)ni * 6 * RC);  // near-field partial-sum slots
+  int32_t* qmap = (int32_t*)(red + (size_t)ni * 6 * RC);  // stored sample of each q
+  int32_t* slots = qmap + Q;                               // near-field partial-sum slots
   const double mu0 = 4.0e-7 * 3.14159265358979323846;
   const int nrow = do_near ? NB.row_ptr[b + 1] - NB.row_ptr[b] : 0;
   const int nslot = do_near ? nrow + NB.col_ptr[b + 1] - NB.col_ptr[b] : 0;
   for (int e = threadIdx.x; e < nslot; e += blockDim.x)
     slots[e] = e < nrow ? NB.prow[NB.row_ptr[b] + e] : NB.pcol[NB.col_blk[NB.col_ptr[b] + e - nrow]];
+  if (do_far)
+    for (int q = threadIdx.x; q < Q; q += blockDim.x) qmap[q] = anti[q];
   const int u0 = NB.box_ptr[b], nu = NB.box_ptr[b + 1] - u0;
   for (int c0 = 0; c0 < W; c0 += RC) {
     if (c0 > 0) __syncthreads();
@@ -478,11 +488,15 @@ __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear N
         for (int c = 0; c < 6 * RC; ++c) acc[c] = mk<TF>(0, 0);
         if (act) {
           const int qa = sl * qs, qb = min(Q, qa + qs);
-          const cx<TF>* mp = M + ((size_t)(j0 + jl) * Q) * 4;
+          const cx<TF>* mp = M + ((size_t)(j0 + jl) * Qh) * 4;
           for (int q = qa; q < qb; ++q) {
+            // receiving factor conj M(q): conj of the stored value for q < Qh,
+            // the stored antipode itself otherwise
+            const cx<TF>* ms = mp + 4 * (size_t)qmap[q];
+            const bool cj = q < Qh;
             cx<TF> m[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) m[k] = conj(mp[4 * (size_t)q + k]);
+            for (int k = 0; k < 4; ++k) m[k] = cj ? conj(ms[k]) : ms[k];
             const cx<TF>* gq = Gs + (size_t)q * ncol;
 #pragma unroll
             for (int r = 0; r < RC; ++r) {
@@ -583,13 +597,14 @@ size_t aggregate_smem(int maxinc, int Q, int nsplit, int RC, int tf_bytes) {
   return (size_t)maxinc * 6 * RC * 2 * tf_bytes + (size_t)(nsplit - 1) * Q * 5 * RC * 2 * tf_bytes + 16;
 }
 size_t receive_smem(int maxinc, int Q, int maxjoin, int RC, int tf_bytes) {
-  return (size_t)Q * 5 * RC * 2 * tf_bytes + (size_t)maxinc * 6 * RC * 2 * tf_bytes + (size_t)maxjoin * 4 + 16;
+  return (size_t)Q * 5 * RC * 2 * tf_bytes + (size_t)maxinc * 6 * RC * 2 * tf_bytes + (size_t)(Q + maxjoin) * 4 +
+         16;
 }
 
 template <typename TF>
-hipError_t launch_moments(const double* pw, int ninc, const double* khat64, int Q, double kappa, void* M,
+hipError_t launch_moments(const double* pw, int ninc, const double* khat64, int Qh, double kappa, void* M,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_moments<TF>, dim3(ninc), dim3(128), 0, st, pw, khat64, Q, kappa, (cx<TF>*)M);
+  hipLaunchKernelGGL(k_moments<TF>, dim3(ninc), dim3(128), 0, st, pw, khat64, Qh, kappa, (cx<TF>*)M);
   return hipGetLastError();
 }
 
@@ -597,14 +612,15 @@ hipError_t launch_moments(const double* pw, int ninc, const double* khat64, int 
 // register group (1, 2 or 4).
 template <typename TF>
 hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, int ldx, int W, int rc,
-                            const void* M, int Q, double w2e, int conjx, int nsplit, void* S, hipStream_t st) {
+                            const void* M, const int32_t* anti, int Q, int Qh, double w2e, int conjx, int nsplit,
+                            void* S, hipStream_t st) {
   if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
   if (nsplit * Q > 256) return hipErrorInvalidValue;
   const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
 #define AGG(RC_)                                                                                               \
   hipLaunchKernelGGL((k_aggregate<TF, RC_>), dim3(xcd_grid(nb)), dim3(256),                                    \
                      aggregate_smem(maxinc, Q, nsplit, RC_, sizeof(TF)), st, I, nb, (const cx<double>*)x, ldx, \
-                     (const cx<TF>*)M, Q, w2e, conjx, nsplit, W, (cx<TF>*)S)
+                     (const cx<TF>*)M, anti, Q, Qh, w2e, conjx, nsplit, W, (cx<TF>*)S)
   if (g == 1) AGG(1); else if (g == 2) AGG(2); else AGG(4);
 #undef AGG
   return hipGetLastError();
@@ -653,14 +669,14 @@ hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, vo
 
 template <typename TF, typename TN>
 hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxinc, int maxjoin,
-                          const void* Gin, const void* M, int Q, const void* part, int W, int rc, int flags,
-                          void* y, int ldy, hipStream_t st) {
+                          const void* Gin, const void* M, const int32_t* anti, int Q, int Qh, const void* part,
+                          int W, int rc, int flags, void* y, int ldy, hipStream_t st) {
   if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
   const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
 #define REC(RC_)                                                                                            \
   hipLaunchKernelGGL((k_receive<TF, TN, RC_>), dim3(xcd_grid(nb)), dim3(256),                               \
                      receive_smem(maxinc, Q, maxjoin, RC_, sizeof(TF)), st, I, B, NB, nb, (const cx<TF>*)Gin, \
-                     (const cx<TF>*)M, Q, (const cx<TN>*)part, flags, W, (cx<double>*)y, ldy)
+                     (const cx<TF>*)M, anti, Q, Qh, (const cx<TN>*)part, flags, W, (cx<double>*)y, ldy)
   if (g == 1) REC(1); else if (g == 2) REC(2); else REC(4);
 #undef REC
   return hipGetLastError();
@@ -678,7 +694,7 @@ hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N,
 #define INST_F(TF)                                                                                            \
   template hipError_t launch_moments<TF>(const double*, int, const double*, int, double, void*, hipStream_t); \
   template hipError_t launch_aggregate<TF>(const DevInc&, int, int, const void*, int, int, int, const void*,   \
-                                           int, double, int, int, void*, hipStream_t);                      \
+                                           const int32_t*, int, int, double, int, int, void*, hipStream_t); \
   template hipError_t launch_shift_up<TF>(const DevLevel&, const DevLevel&, const void*, void*, const void*,  \
                                           const void*, int, int, hipStream_t);                               \
   template hipError_t launch_shift_down<TF>(const DevLevel&, const void*, void*, const void*, const void*,   \
@@ -689,9 +705,9 @@ hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N,
                                             hipStream_t);
 INST_F(float)
 INST_F(double)
-template hipError_t launch_receive<float, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<double, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<float, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<double, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, int, const void*, int, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<float, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, int, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<double, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, int, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<float, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, int, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<double, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, int, int, int, void*, int, hipStream_t);
 
 }  // namespace pie

@@ -21,14 +21,17 @@ hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, in
 // far.hip
 size_t aggregate_smem(int maxinc, int Q, int nsplit, int RC, int tf_bytes);
 size_t receive_smem(int maxinc, int Q, int maxjoin, int RC, int tf_bytes);
-// Per-incidence moment table M[ninc][Q][4] (M0, M1x, M1y, M1z) at the finest level.
+// Per-incidence moment table M[ninc][Qh][4] (M0, M1x, M1y, M1z) at the finest
+// level, for the first Qh samples (the others are antipodes: M(q) = conj
+// M(anti[q])).
 template <typename TF>
-hipError_t launch_moments(const double* pw, int ninc, const double* khat64, int Q, double kappa, void* M,
+hipError_t launch_moments(const double* pw, int ninc, const double* khat64, int Qh, double kappa, void* M,
                           hipStream_t st);
 // W right-hand-side columns per pass, register groups of at most rc columns.
 template <typename TF>
 hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, int ldx, int W, int rc,
-                            const void* M, int Q, double w2e, int conjx, int nsplit, void* S, hipStream_t st);
+                            const void* M, const int32_t* anti, int Q, int Qh, double w2e, int conjx, int nsplit,
+                            void* S, hipStream_t st);
 // Filter tables (Ft for the upward, F for the downward shift) carry SQT
 // trailing zeros.
 template <typename TF>
@@ -43,8 +46,8 @@ hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, vo
                             hipStream_t st);
 template <typename TF, typename TN>
 hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxinc, int maxjoin,
-                          const void* Gin, const void* M, int Q, const void* part, int W, int rc, int flags,
-                          void* y, int ldy, hipStream_t st);
+                          const void* Gin, const void* M, const int32_t* anti, int Q, int Qh, const void* part,
+                          int W, int rc, int flags, void* y, int ldy, hipStream_t st);
 template <typename TN>
 hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N, int R, int conjx, void* xb,
                              hipStream_t st);

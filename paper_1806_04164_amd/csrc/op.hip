@@ -71,7 +71,9 @@ struct pie_op {
   std::vector<double> s_l, kappa_l, d_l;
   int64_t il_pairs = 0;
   // tables in far precision
-  void* dM = nullptr;  // per-incidence moments [ninc][Q][4] in far precision
+  void* dM = nullptr;  // per-incidence moments [ninc][Qh][4] in far precision
+  int Qh = 0;                   // samples stored in the moment table
+  int32_t* dAnti = nullptr;     // [Q] stored sample of each sample (its antipode for q >= Qh)
   std::vector<void*> dTl, dFl, dFtl, dPhl;
   // workspace
   std::vector<void*> dS, dG;
@@ -654,15 +656,39 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   if ((s = dalloc(op, &op->dKhR, 3 * (size_t)op->max_rhs)) || (s = dalloc(op, &op->dPolR, 3 * (size_t)op->max_rhs)) ||
       (s = dalloc(op, &op->dAmpR, 2 * (size_t)op->max_rhs)))
     return s;
-  // ---------------- finest-level moments of every incidence (FP64 phases)
+  // ---------------- finest-level moments of every incidence (FP64 phases).
+  // With an even number of phi samples the sample set is closed under
+  // khat -> -khat: (i, j) -> (n_theta-1-i, j + n_phi/2), and the first Q/2
+  // samples hold one of each antipodal pair, so only they are stored.
   {
+    std::vector<int32_t> anti(Q);
+    op->Qh = Q;
+    for (int q = 0; q < Q; ++q) anti[q] = q;
+    if (op->nph % 2 == 0) {
+      bool ok = true;
+      for (int q = Q / 2; q < Q; ++q) {
+        const int i = q / op->nph, j = q - i * op->nph;
+        const int a = (op->nth - 1 - i) * op->nph + (j + op->nph / 2) % op->nph;
+        double d = 0.0;
+        for (int c = 0; c < 3; ++c) d = std::max(d, std::fabs(khat[3 * (size_t)q + c] + khat[3 * (size_t)a + c]));
+        ok = ok && a < Q / 2 && d < 1e-14;
+        anti[q] = a;
+      }
+      if (ok) {
+        op->Qh = Q / 2;
+      } else {
+        for (int q = 0; q < Q; ++q) anti[q] = q;
+      }
+    }
     unsigned char* mt;
     double* dkh;
-    if ((s = dalloc(op, &mt, (size_t)op->ninc * Q * 4 * cxf)) || (s = upload(op, &dkh, khat))) return s;
+    if ((s = dalloc(op, &mt, (size_t)op->ninc * op->Qh * 4 * cxf)) || (s = upload(op, &dkh, khat)) ||
+        (s = upload(op, &op->dAnti, anti)))
+      return s;
     op->dM = mt;
     hipError_t em = op->far_prec == PIE_FP32
-                        ? launch_moments<float>(op->I.pw, (int)op->ninc, dkh, Q, op->kappa_l[L], mt, st)
-                        : launch_moments<double>(op->I.pw, (int)op->ninc, dkh, Q, op->kappa_l[L], mt, st);
+                        ? launch_moments<float>(op->I.pw, (int)op->ninc, dkh, op->Qh, op->kappa_l[L], mt, st)
+                        : launch_moments<double>(op->I.pw, (int)op->ninc, dkh, op->Qh, op->kappa_l[L], mt, st);
     if (em != hipSuccess) return hip_fail(em, "moments launch");
   }
   // ---------------- near-field fill and diagonal (FP64 arithmetic)
@@ -747,8 +773,8 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
   const DevBasis B = basis(op);
   if (far) {
     if ((e = stage(op, PIE_STAGE_AGGREGATE, st, [&] {
-           return launch_aggregate<TF>(op->I, op->lv[L].nb, op->maxinc, x, ld, R, rcap, op->dM, Q, op->w2e,
-                                       adj, op->nsplit, op->dS[L], st);
+           return launch_aggregate<TF>(op->I, op->lv[L].nb, op->maxinc, x, ld, R, rcap, op->dM, op->dAnti, Q,
+                                       op->Qh, op->w2e, adj, op->nsplit, op->dS[L], st);
          })) != hipSuccess)
       return hip_fail(e, "aggregate");
     if (near_late) {
@@ -791,7 +817,7 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
   if (fork) HIPCHK(hipStreamWaitEvent(st, op->ev_join, 0), "join");
   if ((e = stage(op, PIE_STAGE_RECEIVE, st, [&] {
          return launch_receive<TF, TN>(op->I, B, op->NB, op->lv[L].nb, op->maxinc, op->maxjoin, op->dG[L],
-                                       op->dM, Q, op->dPart, R, rcap, rflags, y, ld, st);
+                                       op->dM, op->dAnti, Q, op->Qh, op->dPart, R, rcap, rflags, y, ld, st);
        })) != hipSuccess)
     return hip_fail(e, "receive");
   return PIE_OK;

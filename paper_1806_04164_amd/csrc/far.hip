@@ -435,13 +435,13 @@ __global__ void __launch_bounds__(512) k_translate(DevLevel Lv, const cx<TF>* __
 //   A = sum_q conj(M1).G_J,  B = sum_q conj(M0) G_J,
 //   Cs = sum_q conj(M0) G_sigma,  Du = sum_q conj(M0) G_u,
 // an RWG half s (r - p), divergence d, tests to  mu0 s (A - (p - C).B) + d Cs
-// and a pulse to Du.  Thread (incidence, quarter of the samples) sums its
-// quarter; the four quarters are added by a fixed butterfly.  Each unknown
+// and a pulse to Du.  Thread (incidence, slice of the samples) sums its
+// slice; the eight slices are added by a fixed butterfly.  Each unknown
 // then adds its halves, its near-field partial sums in a fixed order (slot
 // lists staged in LDS), and is written to its canonical position
 // (conjugated for the adjoint).
 // ---------------------------------------------------------------------------
-constexpr int RECV_SLICES = 4;
+constexpr int RECV_SLICES = 8;  // lanes per incidence (a power of two)
 template <typename TF, typename TN, int RC>
 __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear NB, int nbox,
                                                  const cx<TF>* __restrict__ Gin, const cx<TF>* __restrict__ M,
@@ -478,7 +478,6 @@ __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear N
     }
     __syncthreads();
     if (do_far) {
-      const int qs = (Q + RECV_SLICES - 1) / RECV_SLICES;
       for (int base = 0; base < ni * RECV_SLICES; base += blockDim.x) {
         const int t = base + threadIdx.x;
         const int jl = t / RECV_SLICES, sl = t - jl * RECV_SLICES;
@@ -487,38 +486,56 @@ __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear N
 #pragma unroll
         for (int c = 0; c < 6 * RC; ++c) acc[c] = mk<TF>(0, 0);
         if (act) {
-          const int qa = sl * qs, qb = min(Q, qa + qs);
+          // slice sl takes the samples q = sl (mod RECV_SLICES), so the lanes
+          // of an incidence read adjacent entries of its moment row
           const cx<TF>* mp = M + ((size_t)(j0 + jl) * Qh) * 4;
-          for (int q = qa; q < qb; ++q) {
-            // receiving factor conj M(q): conj of the stored value for q < Qh,
-            // the stored antipode itself otherwise
-            const cx<TF>* ms = mp + 4 * (size_t)qmap[q];
-            const bool cj = q < Qh;
-            cx<TF> m[4];
+          // receiving factor conj M(q): conj of the stored value for q < Qh,
+          // the stored antipode itself otherwise; four samples' moments are
+          // loaded together before their arithmetic
+          constexpr int U = 4;
+          for (int q0 = sl; q0 < Q; q0 += U * RECV_SLICES) {
+            cx<TF> m[U][4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) m[k] = cj ? conj(ms[k]) : ms[k];
-            const cx<TF>* gq = Gs + (size_t)q * ncol;
+            for (int u = 0; u < U; ++u) {
+              const int qu = q0 + u * RECV_SLICES;
+              const int q = qu < Q ? qu : 0;  // in-bounds dummy for the tail
+              const cx<TF>* ms = mp + 4 * (size_t)qmap[q];
 #pragma unroll
-            for (int r = 0; r < RC; ++r) {
+              for (int k = 0; k < 4; ++k) m[u][k] = ms[k];
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                const cx<TF> gc = gq[c * RC + r];
-                cfma(acc[r], m[1 + c], gc);
-                cfma(acc[(1 + c) * RC + r], m[0], gc);
+            for (int u = 0; u < U; ++u) {
+              const int q = q0 + u * RECV_SLICES;
+              if (q < Q) {
+                if (q < Qh) {
+#pragma unroll
+                  for (int k = 0; k < 4; ++k) m[u][k] = conj(m[u][k]);
+                }
+                const cx<TF>* gq = Gs + (size_t)q * ncol;
+#pragma unroll
+                for (int r = 0; r < RC; ++r) {
+#pragma unroll
+                  for (int c = 0; c < 3; ++c) {
+                    const cx<TF> gc = gq[c * RC + r];
+                    cfma(acc[r], m[u][1 + c], gc);
+                    cfma(acc[(1 + c) * RC + r], m[u][0], gc);
+                  }
+                  cfma(acc[4 * RC + r], m[u][0], gq[3 * RC + r]);
+                  cfma(acc[5 * RC + r], m[u][0], gq[4 * RC + r]);
+                }
               }
-              cfma(acc[4 * RC + r], m[0], gq[3 * RC + r]);
-              cfma(acc[5 * RC + r], m[0], gq[4 * RC + r]);
             }
           }
         }
-        // (s0 + s1) + (s2 + s3) across the four lanes of an incidence
+        // fixed butterfly over the RECV_SLICES lanes of an incidence
 #pragma unroll
-        for (int c = 0; c < 6 * RC; ++c) {
-          acc[c].re += __shfl_xor(acc[c].re, 1);
-          acc[c].im += __shfl_xor(acc[c].im, 1);
-          acc[c].re += __shfl_xor(acc[c].re, 2);
-          acc[c].im += __shfl_xor(acc[c].im, 2);
-        }
+        for (int c = 0; c < 6 * RC; ++c)
+#pragma unroll
+          for (int h = 1; h < RECV_SLICES; h <<= 1) {
+            acc[c].re += __shfl_xor(acc[c].re, h);
+            acc[c].im += __shfl_xor(acc[c].im, h);
+          }
         if (act && sl == 0) {
 #pragma unroll
           for (int c = 0; c < 6 * RC; ++c) red[(size_t)jl * 6 * RC + c] = acc[c];

@@ -217,8 +217,10 @@ pie_status pie_profile_read(pie_op* op, double* ms, int64_t* launches);
  *     the caller's stream; PIE_NEAR_FORK_START runs the near field on a
  *     second stream from the start; PIE_NEAR_FORK_AFTER_AGGREGATE forks it
  *     after the finest-level aggregation.  The reception joins it.
- *   il_fork: 1 runs the finest level's interaction-list translation on a
- *     third stream, concurrent with the upward shifts.
+ *   il_fork: 0 keeps the finest level's interaction-list translation on
+ *     the caller's stream; 1 runs it on a third stream forked after the
+ *     aggregation (concurrent with the upward shifts); 2 forks it after
+ *     the first upward shift (concurrent with the coarse levels).
  *   max_chunk: widest register group of RHS columns inside a kernel (1, 2
  *     or 4; the operator's own limit from its LDS budget applies).
  * Default: PIE_NEAR_FORK_START, il_fork 1, max_chunk 4. */
@@ -232,7 +234,7 @@ typedef struct pie_schedule {
   int32_t max_chunk;
 } pie_schedule;
 pie_status pie_schedule_get(const pie_op* op, pie_schedule* out);
-/* PIE_ERR_ARG for an unknown near_fork, il_fork not 0/1 or max_chunk not
+/* PIE_ERR_ARG for an unknown near_fork, il_fork not 0, 1 or 2, or max_chunk not
  * 1, 2 or 4. */
 pie_status pie_schedule_set(pie_op* op, const pie_schedule* sch);
 

@@ -98,6 +98,19 @@ struct DevBasis {
 
 // Stored near-field blocks (a <= b, Morton box indices), row-major n_a x n_b,
 // processed as row-panel tasks of at most one LDS panel each.
+// One row panel [i0, i0 + nr) of a stored near block (a, b): 32 bytes, so a
+// workgroup reads it with one load.
+struct NearTaskDesc {
+  int64_t off;   // entry offset of the panel in the stored blocks
+  int32_t v0;    // first box-order unknown of box b (row sums read x there)
+  int32_t nb;    // unknowns of box b = panel row length
+  int32_t ua;    // box-order unknown of the panel's first row (column sums read x there)
+  int32_t nr;    // rows in the panel
+  int32_t prow;  // partial-sum slot of the panel's first row
+  int32_t pcol;  // partial-sum slot of its column sums, -1 on a diagonal block
+};
+static_assert(sizeof(NearTaskDesc) == 32, "task descriptor is 8 dwords");
+
 struct DevNear {
   int32_t nblk;
   const int32_t* blk_a;
@@ -105,9 +118,7 @@ struct DevNear {
   const int64_t* blk_off;   // entry offset of each block
   const int32_t* prow;      // partial-sum slot of the block's rows
   int32_t ntask;
-  const int32_t* t_blk;     // task -> block
-  const int32_t* t_i0;      // task row range [i0, i1) within the block
-  const int32_t* t_i1;
+  const struct NearTaskDesc* tdesc;  // [ntask] one row panel per SpMM work unit
   const int32_t* pcol;      // task -> partial-sum slot of its column sums (a < b)
   const int32_t* box_ptr;   // [nbL+1] box-order unknown ranges
   const int32_t* row_ptr;   // [nbL+1] blocks whose a is the box

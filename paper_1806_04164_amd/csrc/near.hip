@@ -207,10 +207,11 @@ __global__ void __launch_bounds__(256) k_near_fill(DevGeo G, DevBasis B, DevNear
   const int u0 = NB.box_ptr[a], na = NB.box_ptr[a + 1] - u0;
   const int v0 = NB.box_ptr[b], nb = NB.box_ptr[b + 1] - v0;
   cx<TN>* o = out + NB.blk_off[blk];
+  const int ldz = nb | 1;  // odd row stride of the stored blocks
   for (int e = threadIdx.x; e < na * nb; e += blockDim.x) {
     int i = e / nb, j = e - i * nb;
     cx<double> z = z_entry(G, B, u0 + i, v0 + j, k, w2e);
-    o[e] = mk((TN)z.re, (TN)z.im);
+    o[(size_t)i * ldz + j] = mk((TN)z.re, (TN)z.im);
   }
 }
 
@@ -227,84 +228,159 @@ __global__ void k_diag(DevGeo G, DevBasis B, double* diag_abs, double k, double 
 // r = Z_ab x_b goes to the partial slot of its rows and, for a < b, the
 // transposed part c = Z_ab^T x_a (Z is symmetric) to a column slot.  Work
 // unit = one row panel of one block (at most 16 KiB of entries), so large
-// blocks spread over several workgroups and every workgroup streams one
-// 16-byte-vectorised panel into LDS once; then, for each group of RC of the
-// W right-hand-side columns, threads 0..127 form its row sums (one row each)
-// and threads 128..255 its column sums (one column each, into the panel's
-// own column slot).  The reception kernel adds the slots in a fixed order:
-// no atomics, bitwise reproducible, and each column's arithmetic is the same
-// for any W and RC.
+// blocks spread over several workgroups.  The grid is persistent: each
+// workgroup walks the panels blockIdx.x, blockIdx.x + gridDim.x, ... and
+// holds the next panel's 16-byte loads (and its first right-hand-side
+// group) in registers while it computes the current one from LDS, so the
+// HBM stream never waits for the arithmetic.  Rows are stored with an odd
+// stride (nb | 1), so one-row-per-lane LDS reads are bank-conflict free.
+// For each group of RC of the W columns, threads 0..127 form the row sums
+// (one row each) and threads 128..255 the column sums (one column each,
+// into the panel's own column slot).  The reception kernel adds the slots
+// in a fixed order: no atomics, bitwise reproducible, and each column's
+// arithmetic is the same for any W, RC or grid size.
 // ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// acc[r] += sum_{k0 <= k < k1} zp[k * zs] * xs[k * RC + r], in order of k,
+// with UB LDS reads in flight per step.
+template <typename TN, int RC, int UB>
+__device__ inline void near_dot(const cx<TN>* zp, int zs, const cx<TN>* xs, int k0, int k1, cx<TN> (&acc)[RC]) {
+  int k = k0;
+  for (; k + UB <= k1; k += UB) {
+    cx<TN> z[UB], xv[UB][RC];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      z[u] = zp[(size_t)(k + u) * zs];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) xv[u][r] = xs[(k + u) * RC + r];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < UB; ++u)
+#pragma unroll
+      for (int r = 0; r < RC; ++r) cfma(acc[r], z[u], xv[u][r]);
+  }
+  for (; k < k1; ++k) {
+    const cx<TN> z = zp[(size_t)k * zs];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) cfma(acc[r], z, xs[k * RC + r]);
+  }
+}
+
+// Descriptor of panel `task` from the dword that lane (tid mod 8) loaded.
+__device__ inline NearTaskDesc near_desc(int32_t w) {
+  NearTaskDesc d;
+  d.off = (int64_t)(uint32_t)__builtin_amdgcn_readlane(w, 0) | ((int64_t)__builtin_amdgcn_readlane(w, 1) << 32);
+  d.v0 = __builtin_amdgcn_readlane(w, 2);
+  d.nb = __builtin_amdgcn_readlane(w, 3);
+  d.ua = __builtin_amdgcn_readlane(w, 4);
+  d.nr = __builtin_amdgcn_readlane(w, 5);
+  d.prow = __builtin_amdgcn_readlane(w, 6);
+  d.pcol = __builtin_amdgcn_readlane(w, 7);
+  return d;
+}
+
 template <typename TN, int RC>
-__global__ void __launch_bounds__(256) k_near_spmm(DevNear NB, const cx<TN>* __restrict__ Z,
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(RC == 1 && sizeof(TN) == 4 ? 8 : 1))) k_near_spmm(DevNear NB, const cx<TN>* __restrict__ Z,
                                                    const cx<TN>* __restrict__ xb, int ldx,
                                                    cx<TN>* __restrict__ part, int W) {
-  constexpr int ZCAP = sizeof(TN) == 4 ? 2048 : 1024;   // 16 KiB panel: 8 workgroups per CU
-  constexpr int EPV = 16 / sizeof(cx<TN>);              // entries per 16-byte load
+  constexpr int ZCAP = sizeof(TN) == 4 ? 2048 : 1024;  // 16 KiB panel
+  constexpr int EPV = 16 / sizeof(cx<TN>);             // entries per 16-byte load
+  constexpr int NV = ZCAP / EPV / 256;                 // 16-byte loads per thread
+  constexpr int UB = 4;                                // LDS read batch of the inner products
   __shared__ __align__(16) cx<TN> Zs[ZCAP];
   __shared__ cx<TN> xa_s[128 * RC];
   __shared__ cx<TN> xb_s[128 * RC];
-  const int task = blockIdx.x;
-  const int blk = NB.t_blk[task], i0 = NB.t_i0[task], i1 = NB.t_i1[task];
-  const int a = NB.blk_a[blk], b = NB.blk_b[blk];
-  const int u0 = NB.box_ptr[a];
-  const int v0 = NB.box_ptr[b], nb = NB.box_ptr[b + 1] - v0;
-  const bool offdiag = a != b;
   const int tid = threadIdx.x;
   const int jc = tid - 128;
-  const int nr = i1 - i0;
-  const int cnt = nr * nb;
-  const cx<TN>* src0 = Z + NB.blk_off[blk] + (size_t)i0 * nb;  // 16-byte aligned (host)
-  {
-    const float4* src = (const float4*)src0;
-    float4* dst = (float4*)Zs;
-    const int nv = cnt / EPV;
-    for (int e = tid; e < nv; e += blockDim.x) dst[e] = src[e];
-    if (EPV == 2 && (cnt & 1) && tid == 0) Zs[cnt - 1] = src0[cnt - 1];
-  }
-  for (int c0 = 0; c0 < W; c0 += RC) {
-    if (c0 > 0) __syncthreads();  // the previous group's x staging is consumed
-    if (tid < 128) {
-      if (tid < nb)
+  const int ntask = NB.ntask;
+  // descriptors are read one dword per lane (vector loads, counted with the
+  // panel loads) and broadcast with readlane
+  const int32_t* TW = (const int32_t*)NB.tdesc;
+  f32x4 zr[NV];
+  cx<TN> ztail = mk<TN>(0, 0), xr[RC];
+  // registers <- panel entries and its first column group of x
+  auto fetch = [&](const NearTaskDesc& t) {
+    const int cnt = t.nr * (t.nb | 1), nv = cnt / EPV;
+    const f32x4* src = (const f32x4*)(Z + t.off);
 #pragma unroll
-        for (int r = 0; r < RC; ++r)
-          xb_s[tid * RC + r] = c0 + r < W ? xb[(size_t)(v0 + tid) * ldx + c0 + r] : mk<TN>(0, 0);
-    } else if (offdiag && jc < nr) {
+    for (int v = 0; v < NV; ++v)
+      if (tid + 256 * v < nv) zr[v] = __builtin_nontemporal_load(src + tid + 256 * v);
+    if (EPV == 2 && (cnt & 1) && tid == 0) ztail = Z[t.off + cnt - 1];
+    const int64_t xrow = tid < 128 ? (tid < t.nb ? t.v0 + tid : -1) : (t.pcol >= 0 && jc < t.nr ? t.ua + jc : -1);
 #pragma unroll
-      for (int r = 0; r < RC; ++r)
-        xa_s[jc * RC + r] = c0 + r < W ? xb[(size_t)(u0 + i0 + jc) * ldx + c0 + r] : mk<TN>(0, 0);
+    for (int r = 0; r < RC; ++r)
+      xr[r] = xrow >= 0 && r < W ? xb[xrow * ldx + r] : mk<TN>(0, 0);
+  };
+  int task = blockIdx.x;
+  if (task >= ntask) return;
+  NearTaskDesc t = near_desc(TW[(size_t)task * 8 + (tid & 7)]);
+  fetch(t);
+  int next = task + gridDim.x;
+  int32_t wn = TW[(size_t)min(next, ntask - 1) * 8 + (tid & 7)];
+  for (;;) {
+    // registers -> LDS for the current panel (the previous panel's readers
+    // are past the barrier at the end of its last column group)
+    const int ldz = t.nb | 1;  // odd row stride: the row reads below are bank-conflict free
+    {
+      const int cnt = t.nr * ldz, nv = cnt / EPV;
+      f32x4* dst = (f32x4*)Zs;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (tid + 256 * v < nv) dst[tid + 256 * v] = zr[v];
+      if (EPV == 2 && (cnt & 1) && tid == 0) Zs[cnt - 1] = ztail;
+      if (tid < 128) {
+        if (tid < t.nb)
+#pragma unroll
+          for (int r = 0; r < RC; ++r) xb_s[tid * RC + r] = xr[r];
+      } else if (t.pcol >= 0 && jc < t.nr) {
+#pragma unroll
+        for (int r = 0; r < RC; ++r) xa_s[jc * RC + r] = xr[r];
+      }
     }
-    __syncthreads();
-    if (tid < 128) {
-      if (tid < nr) {
-        cx<TN> racc[RC];
+    const bool more = next < ntask;
+    const NearTaskDesc tn = near_desc(wn);
+    if (more) fetch(tn);  // in flight while this panel is computed
+    const int next2 = next + gridDim.x;
+    wn = TW[(size_t)min(next2, ntask - 1) * 8 + (tid & 7)];
+    for (int c0 = 0; c0 < W; c0 += RC) {
+      if (c0 > 0) {
+        __syncthreads();  // the previous group's x staging is consumed
+        if (tid < 128) {
+          if (tid < t.nb)
 #pragma unroll
-        for (int r = 0; r < RC; ++r) racc[r] = mk<TN>(0, 0);
-        const cx<TN>* zr = Zs + (size_t)tid * nb;
-        for (int j = 0; j < nb; ++j) {
-          const cx<TN> z = zr[j];
+            for (int r = 0; r < RC; ++r)
+              xb_s[tid * RC + r] = c0 + r < W ? xb[(size_t)(t.v0 + tid) * ldx + c0 + r] : mk<TN>(0, 0);
+        } else if (t.pcol >= 0 && jc < t.nr) {
 #pragma unroll
-          for (int r = 0; r < RC; ++r) cfma(racc[r], z, xb_s[j * RC + r]);
+          for (int r = 0; r < RC; ++r)
+            xa_s[jc * RC + r] = c0 + r < W ? xb[(size_t)(t.ua + jc) * ldx + c0 + r] : mk<TN>(0, 0);
         }
-        cx<TN>* prow = part + ((size_t)NB.prow[blk] + i0 + tid) * W + c0;
+      }
+      __syncthreads();
+      // one thread per row (threads 0..127) or column (128..255)
+      const bool is_row = tid < 128;
+      const int idx = is_row ? tid : jc;
+      if (is_row ? idx < t.nr : (t.pcol >= 0 && idx < t.nb)) {
+        cx<TN> acc[RC];
+#pragma unroll
+        for (int r = 0; r < RC; ++r) acc[r] = mk<TN>(0, 0);
+        if (is_row)
+          near_dot<TN, RC, UB>(Zs + (size_t)idx * ldz, 1, xb_s, 0, t.nb, acc);
+        else
+          near_dot<TN, RC, UB>(Zs + idx, ldz, xa_s, 0, t.nr, acc);
+        cx<TN>* o = part + ((size_t)(is_row ? t.prow : t.pcol) + idx) * W + c0;
 #pragma unroll
         for (int r = 0; r < RC; ++r)
-          if (c0 + r < W) prow[r] = racc[r];
+          if (c0 + r < W) o[r] = acc[r];
       }
-    } else if (offdiag && jc < nb) {
-      cx<TN> cacc[RC];
-#pragma unroll
-      for (int r = 0; r < RC; ++r) cacc[r] = mk<TN>(0, 0);
-      for (int i = 0; i < nr; ++i) {
-        const cx<TN> z = Zs[(size_t)i * nb + jc];
-#pragma unroll
-        for (int r = 0; r < RC; ++r) cfma(cacc[r], z, xa_s[i * RC + r]);
-      }
-      cx<TN>* pcol = part + ((size_t)NB.pcol[task] + jc) * W + c0;
-#pragma unroll
-      for (int r = 0; r < RC; ++r)
-        if (c0 + r < W) pcol[r] = cacc[r];
     }
+    if (!more) break;
+    __syncthreads();  // every reader of Zs / x staging is done
+    t = tn;
+    next = next2;
   }
 }
 
@@ -340,9 +416,21 @@ hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, in
   if (NB.ntask == 0) return hipSuccess;
   if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
   const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
-#define NS(G_)                                                                                  \
-  hipLaunchKernelGGL((k_near_spmm<TN, G_>), dim3(NB.ntask), dim3(256), 0, st, NB, (const cx<TN>*)Z, \
-                     (const cx<TN>*)xb, ldx, (cx<TN>*)part, W)
+  // persistent grid: as many workgroups as fit on the device at once
+#define NS(G_)                                                                                       \
+  do {                                                                                               \
+    static int wgs = 0;                                                                              \
+    if (wgs == 0) {                                                                                  \
+      int per_cu = 0, dev = 0, ncu = 0;                                                              \
+      hipError_t e_ = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_near_spmm<TN, G_>, 256, 0); \
+      if (e_ == hipSuccess) e_ = hipGetDevice(&dev);                                                 \
+      if (e_ == hipSuccess) e_ = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev); \
+      if (e_ != hipSuccess) return e_;                                                               \
+      wgs = std::max(1, per_cu) * std::max(1, ncu);                                                  \
+    }                                                                                                \
+    hipLaunchKernelGGL((k_near_spmm<TN, G_>), dim3(std::min(NB.ntask, wgs)), dim3(256), 0, st, NB,   \
+                       (const cx<TN>*)Z, (const cx<TN>*)xb, ldx, (cx<TN>*)part, W);                  \
+  } while (0)
   if (g == 1) NS(1); else if (g == 2) NS(2); else NS(4);
 #undef NS
   return hipGetLastError();

@@ -300,7 +300,8 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   // panels stay 16-byte aligned), one SpMM workgroup per panel
   const int zcap = op->near_prec == PIE_FP32 ? 2048 : 1024;
   std::vector<int32_t> ba, bb, prow, row_ptr(nbL + 1, 0), col_ptr(nbL + 1, 0), col_blk;
-  std::vector<int32_t> tbk, ti0, ti1, tpc;
+  std::vector<int32_t> tpc;
+  std::vector<NearTaskDesc> tdesc;
   std::vector<int64_t> boff;
   std::vector<std::vector<int32_t>> cols(nbL);
   int64_t off = 0, slot = 0, entries = 0;
@@ -313,24 +314,33 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
       ba.push_back(a);
       bb.push_back(b);
       boff.push_back(off);
-      off += ((int64_t)na * nb + 3) & ~int64_t(3);  // 4-entry (32-byte FP32) aligned blocks
+      // rows stored with an odd stride nb | 1, so that the SpMM's row-wise
+      // LDS reads (one row per lane) hit distinct banks
+      const int ldz = nb | 1;
+      off += ((int64_t)na * ldz + 3) & ~int64_t(3);  // 4-entry (32-byte FP32) aligned blocks
       entries += (int64_t)na * nb;
       prow.push_back((int32_t)slot);
       slot += na;
-      int rpp = std::min(128, zcap / nb);
-      if (op->near_prec == PIE_FP32 && (nb & 1) && rpp > 1) rpp &= ~1;
+      int rpp = std::min(128, zcap / ldz);
+      if (op->near_prec == PIE_FP32 && rpp > 1) rpp &= ~1;  // even row starts: 16-byte aligned panels
       for (int i0 = 0; i0 < na; i0 += rpp) {
-        int tid_ = (int)tbk.size();
-        tbk.push_back(id);
-        ti0.push_back(i0);
-        ti1.push_back(std::min(na, i0 + rpp));
+        int tid_ = (int)tdesc.size();
+        NearTaskDesc d;
+        d.off = boff[id] + (int64_t)i0 * ldz;
+        d.v0 = box_ptr[b];
+        d.nb = nb;
+        d.ua = box_ptr[a] + i0;
+        d.nr = std::min(na, i0 + rpp) - i0;
+        d.prow = prow[id] + i0;
         if (b != a) {
-          tpc.push_back((int32_t)slot);
+          d.pcol = (int32_t)slot;
           slot += nb;
           cols[b].push_back(tid_);
         } else {
-          tpc.push_back(-1);
+          d.pcol = -1;
         }
+        tpc.push_back(d.pcol);
+        tdesc.push_back(d);
       }
     }
     row_ptr[a + 1] = (int32_t)ba.size();
@@ -342,15 +352,16 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   op->near_stored = off;
   op->near_entries = entries;
   op->nslots = slot;
-  op->ntask = (int64_t)tbk.size();
-  int32_t *dba, *dbb, *dprow, *dbp, *drp, *dcp, *dcb, *dtb, *dti0, *dti1, *dtpc;
+  op->ntask = (int64_t)tdesc.size();
+  int32_t *dba, *dbb, *dprow, *dbp, *drp, *dcp, *dcb, *dtpc;
   int64_t* dbo;
+  NearTaskDesc* dtd;
   if ((s = upload(op, &dba, ba)) || (s = upload(op, &dbb, bb)) || (s = upload(op, &dbo, boff)) ||
       (s = upload(op, &dprow, prow)) || (s = upload(op, &dbp, box_ptr)) || (s = upload(op, &drp, row_ptr)) ||
-      (s = upload(op, &dcp, col_ptr)) || (s = upload(op, &dcb, col_blk)) || (s = upload(op, &dtb, tbk)) ||
-      (s = upload(op, &dti0, ti0)) || (s = upload(op, &dti1, ti1)) || (s = upload(op, &dtpc, tpc)))
+      (s = upload(op, &dcp, col_ptr)) || (s = upload(op, &dcb, col_blk)) || (s = upload(op, &dtd, tdesc)) ||
+      (s = upload(op, &dtpc, tpc)))
     return s;
-  op->NB = DevNear{(int32_t)ba.size(), dba, dbb, dbo, dprow, (int32_t)tbk.size(), dtb, dti0, dti1, dtpc,
+  op->NB = DevNear{(int32_t)ba.size(), dba, dbb, dbo, dprow, (int32_t)tdesc.size(), dtd, dtpc,
                    dbp, drp, dcp, dcb};
   // ---------------- incidences
   std::vector<int32_t> iptr(nbL + 1, 0), itri, irwg, ifv, ipulse, uslot(2 * (size_t)N, -1);
@@ -695,6 +706,7 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   unsigned char* nz;
   if ((s = dalloc(op, &nz, (size_t)op->near_stored * cxn))) return s;
   op->dNear = nz;
+  HIPCHK(hipMemset(nz, 0, (size_t)op->near_stored * cxn), "near clear");  // row padding and block tails
   hipError_t e = op->near_prec == PIE_FP32 ? launch_near_fill<float>(G, B, op->NB, nz, op->k, op->w2e, st)
                                            : launch_near_fill<double>(G, B, op->NB, nz, op->k, op->w2e, st);
   if (e != hipSuccess) return hip_fail(e, "near fill launch");
@@ -782,25 +794,37 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
       if (ps) return ps;
     }
     // finest-level translation on the third stream, concurrent with the
-    // upward shifts and the coarser translations
+    // upward shifts and the coarser translations; forked after the
+    // aggregation (il_fork 1) or after the first upward shift (il_fork 2),
+    // so that it overlaps the small coarse-level kernels instead
     const bool fork2 = L > 3 && op->sched_il;
     auto translate = [&](int l, hipStream_t s) {
       return stage(op, PIE_STAGE_TRANSLATE, s, [&] {
         return launch_translate<TF>(op->lv[l], op->dS[l], op->dTl[l], op->dG[l], Q, R, s);
       });
     };
-    if (fork2) {
+    auto fork_translate = [&]() -> pie_status {
       HIPCHK(hipEventRecord(op->ev_agg, st), "fork");
       HIPCHK(hipStreamWaitEvent(op->side2, op->ev_agg, 0), "fork");
       if ((e = translate(L, op->side2)) != hipSuccess) return hip_fail(e, "translate");
       HIPCHK(hipEventRecord(op->ev_il, op->side2), "join");
+      return PIE_OK;
+    };
+    if (fork2 && op->sched_il == 1) {
+      pie_status ps = fork_translate();
+      if (ps) return ps;
     }
-    for (int l = L - 1; l >= 3; --l)
+    for (int l = L - 1; l >= 3; --l) {
       if ((e = stage(op, PIE_STAGE_SHIFT_UP, st, [&] {
              return launch_shift_up<TF>(op->lv[l], op->lv[l + 1], op->dS[l + 1], op->dS[l], op->dFtl[l],
                                         op->dPhl[l], Q, R, st);
            })) != hipSuccess)
         return hip_fail(e, "shift up");
+      if (l == L - 1 && fork2 && op->sched_il == 2) {
+        pie_status ps = fork_translate();
+        if (ps) return ps;
+      }
+    }
     for (int l = 3; l <= L; ++l)
       if (l < L || !fork2)
         if ((e = translate(l, st)) != hipSuccess) return hip_fail(e, "translate");
@@ -1132,7 +1156,7 @@ pie_status pie_schedule_set(pie_op* op, const pie_schedule* sch) {
     return PIE_ERR_ARG;
   }
   if (sch->near_fork < PIE_NEAR_SERIAL || sch->near_fork > PIE_NEAR_FORK_AFTER_AGGREGATE ||
-      (sch->il_fork != 0 && sch->il_fork != 1) ||
+      (sch->il_fork < 0 || sch->il_fork > 2) ||
       (sch->max_chunk != 1 && sch->max_chunk != 2 && sch->max_chunk != 4)) {
     pie::set_error("invalid schedule");
     return PIE_ERR_ARG;
@@ -1163,7 +1187,7 @@ pie_status pie_autotune(pie_op* op, const void* x, void* y, int64_t R, int32_t r
   double best_ms = 1e300;
   s = PIE_OK;
   for (int nf = PIE_NEAR_SERIAL; nf <= PIE_NEAR_FORK_AFTER_AGGREGATE && !s; ++nf)
-    for (int il = 0; il <= 1 && !s; ++il)
+    for (int il = 0; il <= 2 && !s; ++il)
       for (int ch : {4, 2, 1}) {
         // register groups wider than R or than the operator's limit repeat a narrower one
         if (ch > 1 && (ch > op->rc || ch > R)) continue;

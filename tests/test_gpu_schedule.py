@@ -45,7 +45,7 @@ def test_schedules_bitwise_equal(s4, near, far):
     ref = op.matvec(x).cpu().numpy()
     refa = op.matvec(x, adjoint=True).cpu().numpy()
     for nf, il, ch in itertools.product((PIE_NEAR_SERIAL, PIE_NEAR_FORK_START, PIE_NEAR_FORK_AFTER_AGGREGATE),
-                                        (0, 1), (1, 2, 4)):
+                                        (0, 1, 2), (1, 2, 4)):
         op.schedule = dict(near_fork=nf, il_fork=il, max_chunk=ch)
         assert op.schedule == dict(near_fork=nf, il_fork=il, max_chunk=ch)
         y = op.matvec(x).cpu().numpy()
@@ -57,7 +57,7 @@ def test_schedules_bitwise_equal(s4, near, far):
 
 def test_schedule_validation(s4):
     op = _op(s4, max_rhs=1)
-    for bad in (dict(near_fork=3), dict(il_fork=2), dict(max_chunk=3)):
+    for bad in (dict(near_fork=3), dict(il_fork=3), dict(max_chunk=3)):
         with pytest.raises(PieError):
             op.schedule = bad
 

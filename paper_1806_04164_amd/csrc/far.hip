@@ -65,11 +65,12 @@ __global__ void __launch_bounds__(128) k_moments(const double* __restrict__ pw, 
 
 // Workgroup = one finest box; the W right-hand-side columns are taken in
 // groups of RC.  Stage 1: thread per (incidence, column) forms the
-// coefficients (a, -b, xp, cu) in LDS.  Stage 2: thread (g, q) adds the
-// incidences j = g (mod nsplit) in order, four incidences' moments in flight
-// (the box's moments are re-read from L2 for later groups); stage 3 adds
-// the nsplit slices in a fixed order.  Each column's arithmetic is the same
-// for any W and RC.
+// coefficients (a, -b, xp, cu) in LDS.  Stage 2: thread (g, s) adds the
+// incidences j = g (mod nsplit) in order for the stored sample s and its
+// antipode, two (FP64) or four (FP32) incidences' moments in flight (the
+// box's moments are re-read from L2 for later groups); stage 3 adds the
+// nsplit slices in a fixed order.  Each column's arithmetic is the same for
+// any W and RC.
 template <typename TF, int RC>
 __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<double>* __restrict__ x, int ldx,
                                                    const cx<TF>* __restrict__ M, const int32_t* __restrict__ anti,
@@ -82,10 +83,11 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
   constexpr int ncol = 5 * RC;
   cx<TF>* cf = (cx<TF>*)smem;                      // [ni][6][RC]: a, -bx, -by, -bz, xp, cu
   cx<TF>* part = cf + (size_t)ni * 6 * RC;         // [nsplit - 1][Q][5][RC]
-  const int g = threadIdx.x / Q, q = threadIdx.x - g * Q;
+  int32_t* pair = (int32_t*)(part + (size_t)(nsplit - 1) * Q * ncol);  // [Qh] antipode of a stored sample
+  const bool paired = Qh < Q;
+  const int g = threadIdx.x / Qh, sq = threadIdx.x - g * Qh;  // group, stored sample
   const bool act = g < nsplit;
-  const int qm = act ? anti[q] : 0;      // stored sample of q
-  const bool cjm = q >= Qh;              // M(q) = conj M(qm)
+  for (int q = Qh + threadIdx.x; q < Q; q += blockDim.x) pair[anti[q]] = q;
   for (int c0 = 0; c0 < W; c0 += RC) {
     if (c0 > 0) __syncthreads();
     for (int e = threadIdx.x; e < ni * RC; e += blockDim.x) {
@@ -125,19 +127,34 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
       o[5 * RC] = mk((TF)cu.re, (TF)cu.im);
     }
     __syncthreads();
-    cx<TF> acc[ncol];
+    // sample sq takes M(sq), its antipode pair[sq] takes conj M(sq): every
+    // stored moment is loaded once and used twice
+    cx<TF> acc[ncol], acc2[ncol];
 #pragma unroll
-    for (int c = 0; c < ncol; ++c) acc[c] = mk<TF>(0, 0);
+    for (int c = 0; c < ncol; ++c) acc[c] = acc2[c] = mk<TF>(0, 0);
+    auto add = [&](cx<TF>(&ac)[ncol], const cx<TF>(&mm)[4], const cx<TF>* c6) {
+#pragma unroll
+      for (int r = 0; r < RC; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          cfma(ac[c * RC + r], c6[r], mm[1 + c]);
+          cfma(ac[c * RC + r], c6[(1 + c) * RC + r], mm[0]);
+        }
+        cfma(ac[3 * RC + r], c6[4 * RC + r], mm[0]);
+        cfma(ac[4 * RC + r], c6[5 * RC + r], mm[0]);
+      }
+    };
+    const int q2 = act && paired ? pair[sq] : 0;
     if (act) {
-      constexpr int U = 4;
+      constexpr int U = sizeof(TF) == 8 ? 2 : 4;
       for (int jl = g; jl < ni; jl += U * nsplit) {
         cx<TF> m[U][4];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int jj = jl + u * nsplit;
-          const cx<TF>* mp = M + ((size_t)(j0 + (jj < ni ? jj : jl)) * Qh + qm) * 4;
+          const cx<TF>* mp = M + ((size_t)(j0 + (jj < ni ? jj : jl)) * Qh + sq) * 4;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) m[u][t] = cjm ? conj(mp[t]) : mp[t];
+          for (int t = 0; t < 4; ++t) m[u][t] = mp[t];
         }
         __builtin_amdgcn_sched_barrier(0);  // keep the incidences' loads in flight together
 #pragma unroll
@@ -145,38 +162,49 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
           const int jj = jl + u * nsplit;
           if (jj < ni) {
             const cx<TF>* c6 = cf + (size_t)jj * 6 * RC;
+            add(acc, m[u], c6);
+            if (paired) {
+              cx<TF> cm[4];
 #pragma unroll
-            for (int r = 0; r < RC; ++r) {
-#pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                cfma(acc[c * RC + r], c6[r], m[u][1 + c]);
-                cfma(acc[c * RC + r], c6[(1 + c) * RC + r], m[u][0]);
-              }
-              cfma(acc[3 * RC + r], c6[4 * RC + r], m[u][0]);
-              cfma(acc[4 * RC + r], c6[5 * RC + r], m[u][0]);
+              for (int t = 0; t < 4; ++t) cm[t] = conj(m[u][t]);
+              add(acc2, cm, c6);
             }
           }
         }
       }
       if (g > 0) {
-        cx<TF>* pp = part + ((size_t)(g - 1) * Q + q) * ncol;
+        cx<TF>* pp = part + ((size_t)(g - 1) * Q + sq) * ncol;
 #pragma unroll
         for (int c = 0; c < ncol; ++c) pp[c] = acc[c];
+        if (paired) {
+          cx<TF>* p2 = part + ((size_t)(g - 1) * Q + q2) * ncol;
+#pragma unroll
+          for (int c = 0; c < ncol; ++c) p2[c] = acc2[c];
+        }
       }
     }
     __syncthreads();
     if (act && g == 0) {
       for (int h = 1; h < nsplit; ++h) {
-        const cx<TF>* pp = part + ((size_t)(h - 1) * Q + q) * ncol;
+        const cx<TF>* pp = part + ((size_t)(h - 1) * Q + sq) * ncol;
+        const cx<TF>* p2 = part + ((size_t)(h - 1) * Q + q2) * ncol;
 #pragma unroll
-        for (int c = 0; c < ncol; ++c) acc[c] = acc[c] + pp[c];
+        for (int c = 0; c < ncol; ++c) {
+          acc[c] = acc[c] + pp[c];
+          if (paired) acc2[c] = acc2[c] + p2[c];
+        }
       }
 #pragma unroll
       for (int r = 0; r < RC; ++r)
         if (c0 + r < W) {
-          cx<TF>* o = S + (((size_t)b * W + c0 + r) * Q + q) * 5;
+          cx<TF>* o = S + (((size_t)b * W + c0 + r) * Q + sq) * 5;
 #pragma unroll
           for (int k = 0; k < 5; ++k) o[k] = acc[k * RC + r];
+          if (paired) {
+            cx<TF>* o2 = S + (((size_t)b * W + c0 + r) * Q + q2) * 5;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) o2[k] = acc2[k * RC + r];
+          }
         }
     }
   }
@@ -435,15 +463,17 @@ __global__ void __launch_bounds__(512) k_translate(DevLevel Lv, const cx<TF>* __
 //   A = sum_q conj(M1).G_J,  B = sum_q conj(M0) G_J,
 //   Cs = sum_q conj(M0) G_sigma,  Du = sum_q conj(M0) G_u,
 // an RWG half s (r - p), divergence d, tests to  mu0 s (A - (p - C).B) + d Cs
-// and a pulse to Du.  Thread (incidence, slice of the samples) sums its
-// slice; the eight slices are added by a fixed butterfly.  Each unknown
+// and a pulse to Du.  Thread (incidence, slice of the stored samples) sums
+// its slice, each stored sample s together with its antipode (receiving
+// factors conj M(s) and M(s)); the eight slices are added by a fixed
+// butterfly.  Each unknown
 // then adds its halves, its near-field partial sums in a fixed order (slot
 // lists staged in LDS), and is written to its canonical position
 // (conjugated for the adjoint).
 // ---------------------------------------------------------------------------
 constexpr int RECV_SLICES = 8;  // lanes per incidence (a power of two)
 template <typename TF, typename TN, int RC>
-__global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear NB, int nbox,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 1 ? 4 : 1))) k_receive(DevInc I, DevBasis B, DevNear NB, int nbox,
                                                  const cx<TF>* __restrict__ Gin, const cx<TF>* __restrict__ M,
                                                  const int32_t* __restrict__ anti, int Q, int Qh,
                                                  const cx<TN>* __restrict__ part, int flags, int W,
@@ -456,15 +486,15 @@ __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear N
   const bool do_far = flags & 2, do_near = flags & 1, conj_out = flags & 4;
   cx<TF>* Gs = (cx<TF>*)smem;                              // [Q][5][RC]
   cx<TF>* red = Gs + (size_t)Q * ncol;                     // [ni][6][RC]: A, Bx, By, Bz, Cs, Du
-  int32_t* qmap = (int32_t*)(red + (size_t)ni * 6 * RC);  // stored sample of each q
-  int32_t* slots = qmap + Q;                               // near-field partial-sum slots
+  int32_t* pair = (int32_t*)(red + (size_t)ni * 6 * RC);  // [Qh] antipode of each stored sample
+  int32_t* slots = pair + Q;                               // near-field partial-sum slots
   const double mu0 = 4.0e-7 * 3.14159265358979323846;
   const int nrow = do_near ? NB.row_ptr[b + 1] - NB.row_ptr[b] : 0;
   const int nslot = do_near ? nrow + NB.col_ptr[b + 1] - NB.col_ptr[b] : 0;
   for (int e = threadIdx.x; e < nslot; e += blockDim.x)
     slots[e] = e < nrow ? NB.prow[NB.row_ptr[b] + e] : NB.pcol[NB.col_blk[NB.col_ptr[b] + e - nrow]];
   if (do_far)
-    for (int q = threadIdx.x; q < Q; q += blockDim.x) qmap[q] = anti[q];
+    for (int q = Qh + threadIdx.x; q < Q; q += blockDim.x) pair[anti[q]] = q;
   const int u0 = NB.box_ptr[b], nu = NB.box_ptr[b + 1] - u0;
   for (int c0 = 0; c0 < W; c0 += RC) {
     if (c0 > 0) __syncthreads();
@@ -486,44 +516,47 @@ __global__ void __launch_bounds__(256) k_receive(DevInc I, DevBasis B, DevNear N
 #pragma unroll
         for (int c = 0; c < 6 * RC; ++c) acc[c] = mk<TF>(0, 0);
         if (act) {
-          // slice sl takes the samples q = sl (mod RECV_SLICES), so the lanes
-          // of an incidence read adjacent entries of its moment row
+          // slice sl takes the stored samples s = sl (mod RECV_SLICES), so the
+          // lanes of an incidence read adjacent entries of its moment row.
+          // The receiving factor of sample s is conj M(s); that of its
+          // antipode pair[s] (when stored samples are halved) is M(s)
+          // itself, so every stored moment is loaded once and used twice.
+          // Four samples' moments are loaded together before their arithmetic.
           const cx<TF>* mp = M + ((size_t)(j0 + jl) * Qh) * 4;
-          // receiving factor conj M(q): conj of the stored value for q < Qh,
-          // the stored antipode itself otherwise; four samples' moments are
-          // loaded together before their arithmetic
+          auto recv = [&](const cx<TF>(&mm)[4], int q) {
+            const cx<TF>* gq = Gs + (size_t)q * ncol;
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                const cx<TF> gc = gq[c * RC + r];
+                cfma(acc[r], mm[1 + c], gc);
+                cfma(acc[(1 + c) * RC + r], mm[0], gc);
+              }
+              cfma(acc[4 * RC + r], mm[0], gq[3 * RC + r]);
+              cfma(acc[5 * RC + r], mm[0], gq[4 * RC + r]);
+            }
+          };
           constexpr int U = 4;
-          for (int q0 = sl; q0 < Q; q0 += U * RECV_SLICES) {
+          for (int s0 = sl; s0 < Qh; s0 += U * RECV_SLICES) {
             cx<TF> m[U][4];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-              const int qu = q0 + u * RECV_SLICES;
-              const int q = qu < Q ? qu : 0;  // in-bounds dummy for the tail
-              const cx<TF>* ms = mp + 4 * (size_t)qmap[q];
+              const int su = s0 + u * RECV_SLICES;
+              const cx<TF>* ms = mp + 4 * (size_t)(su < Qh ? su : 0);  // in-bounds dummy for the tail
 #pragma unroll
               for (int k = 0; k < 4; ++k) m[u][k] = ms[k];
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-              const int q = q0 + u * RECV_SLICES;
-              if (q < Q) {
-                if (q < Qh) {
+              const int su = s0 + u * RECV_SLICES;
+              if (su < Qh) {
+                cx<TF> cm[4];
 #pragma unroll
-                  for (int k = 0; k < 4; ++k) m[u][k] = conj(m[u][k]);
-                }
-                const cx<TF>* gq = Gs + (size_t)q * ncol;
-#pragma unroll
-                for (int r = 0; r < RC; ++r) {
-#pragma unroll
-                  for (int c = 0; c < 3; ++c) {
-                    const cx<TF> gc = gq[c * RC + r];
-                    cfma(acc[r], m[u][1 + c], gc);
-                    cfma(acc[(1 + c) * RC + r], m[u][0], gc);
-                  }
-                  cfma(acc[4 * RC + r], m[u][0], gq[3 * RC + r]);
-                  cfma(acc[5 * RC + r], m[u][0], gq[4 * RC + r]);
-                }
+                for (int k = 0; k < 4; ++k) cm[k] = conj(m[u][k]);
+                recv(cm, su);
+                if (Qh < Q) recv(m[u], pair[su]);
               }
             }
           }
@@ -611,7 +644,8 @@ __global__ void k_permute_in(const cx<double>* __restrict__ x, int ldx, const in
 
 // ------------------------------------------------------------- launchers --
 size_t aggregate_smem(int maxinc, int Q, int nsplit, int RC, int tf_bytes) {
-  return (size_t)maxinc * 6 * RC * 2 * tf_bytes + (size_t)(nsplit - 1) * Q * 5 * RC * 2 * tf_bytes + 16;
+  return (size_t)maxinc * 6 * RC * 2 * tf_bytes + (size_t)(nsplit - 1) * Q * 5 * RC * 2 * tf_bytes +
+         (size_t)Q * 4 + 16;
 }
 size_t receive_smem(int maxinc, int Q, int maxjoin, int RC, int tf_bytes) {
   return (size_t)Q * 5 * RC * 2 * tf_bytes + (size_t)maxinc * 6 * RC * 2 * tf_bytes + (size_t)(Q + maxjoin) * 4 +
@@ -632,7 +666,7 @@ hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, 
                             const void* M, const int32_t* anti, int Q, int Qh, double w2e, int conjx, int nsplit,
                             void* S, hipStream_t st) {
   if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
-  if (nsplit * Q > 256) return hipErrorInvalidValue;
+  if (nsplit * Qh > 256) return hipErrorInvalidValue;
   const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
 #define AGG(RC_)                                                                                               \
   hipLaunchKernelGGL((k_aggregate<TF, RC_>), dim3(xcd_grid(nb)), dim3(256),                                    \

@@ -642,11 +642,6 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     set_error("more than 256 k-space samples per level are not supported");
     return PIE_ERR_UNSUPPORTED;
   }
-  {
-    const int rcm = op->rc <= 1 ? 1 : (op->rc <= 2 ? 2 : 4);
-    op->nsplit = 256 / Q < 1 ? 1 : 256 / Q;
-    while (op->nsplit > 1 && aggregate_smem(op->maxinc, Q, op->nsplit, rcm, tfb) > 65536) --op->nsplit;
-  }
   // ---------------- workspace (one pass of pw RHS columns)
   op->pw = std::min(op->max_rhs, kPassMax);
   const size_t cxf = 2 * (size_t)tfb, cxn = op->near_prec == PIE_FP32 ? 8 : 16;
@@ -691,6 +686,10 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
         for (int q = 0; q < Q; ++q) anti[q] = q;
       }
     }
+    // aggregation: one lane per stored sample, nsplit incidence groups
+    const int rcm = op->rc <= 1 ? 1 : (op->rc <= 2 ? 2 : 4);
+    op->nsplit = 256 / op->Qh < 1 ? 1 : 256 / op->Qh;
+    while (op->nsplit > 1 && aggregate_smem(op->maxinc, Q, op->nsplit, rcm, tfb) > 65536) --op->nsplit;
     unsigned char* mt;
     double* dkh;
     if ((s = dalloc(op, &mt, (size_t)op->ninc * op->Qh * 4 * cxf)) || (s = upload(op, &dkh, khat)) ||

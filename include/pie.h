@@ -238,8 +238,9 @@ pie_status pie_schedule_get(const pie_op* op, pie_schedule* out);
  * 1, 2 or 4. */
 pie_status pie_schedule_set(pie_op* op, const pie_schedule* sch);
 
-/* Autotuner: times every distinct schedule on R right-hand sides (one
- * warm-up, then reps MVMs each, HIP events on stream), keeps the fastest
+/* Autotuner: times every distinct schedule on R right-hand sides in two
+ * rounds (each round one warm-up, then reps MVMs per schedule, HIP events
+ * on stream; a schedule's time is its faster round), keeps the fastest
  * on the operator and returns it in *chosen and its time per MVM in *ms
  * (either may be NULL).  x, y: caller-owned device complex128 [N][R] work
  * vectors (x is read, y overwritten).  Stage profiling must be off.

@@ -265,11 +265,11 @@ __device__ __forceinline__ void shift_mac(const TF* Fs, int qa, int qb, LD load,
 struct ShiftItem {
   int g, q0, r;
 };
-__device__ __forceinline__ bool shift_item(int ngroup, int ntile, int R, ShiftItem& it) {
+__device__ __forceinline__ bool shift_item(int ngroup, int ntile, int R, int rows, ShiftItem& it) {
   const int per = (ngroup + 7) >> 3, w = blockIdx.x, x = w & 7, j = w >> 3;
   const int sub = ntile * R, gl = j / sub, rem = j - gl * sub;
   it.g = x * per + gl;
-  it.q0 = (rem / R) * SQT;
+  it.q0 = (rem / R) * rows;
   it.r = rem - (rem / R) * R;
   return gl < per && it.g < ngroup;
 }
@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(256) k_shift_up(DevLevel Lp, DevLevel Lc,
   cx<TF>* part = (cx<TF>*)smem;                               // [slice][lane][SQT]
   TF* Fs = (TF*)(part + (size_t)SHIFT_SLICES * SHIFT_LANES * SQT);  // [Q][SQT]
   ShiftItem it;
-  if (!shift_item(Lp.nug, ntile, R, it)) return;
+  if (!shift_item(Lp.nug, ntile, R, SQT, it)) return;
   const int q0 = it.q0, r = it.r;
   const int nq = min(SQT, Q - q0);
   shift_tile(Ft, Fs, Q, q0);
@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
   TF* Fs = (TF*)(part + (size_t)SHIFT_SLICES * SHIFT_LANES * SQT);  // [Q][SQT]
   const int ng = (Lc.nb + SHIFT_GROUP - 1) / SHIFT_GROUP;
   ShiftItem it;
-  if (!shift_item(ng, ntile, R, it)) return;
+  if (!shift_item(ng, ntile, R, SQT, it)) return;
   const int q0 = it.q0, r = it.r;
   const int nq = min(SQT, Q - q0);
   shift_tile(F, Fs, Q, q0);
@@ -376,6 +376,219 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
 #pragma unroll
     for (int i = 0; i < SQT; ++i)
       if (i < nq) o[(size_t)i * 5] = o[(size_t)i * 5] + acc[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 shifts on the matrix cores.  The filter product is a real GEMM
+//   D[q][col] = sum_q' F[q][q'] B[q'][col],  col = (child, component, re/im),
+// over the ten real columns of each child of a group (at most SHIFT_GROUP
+// children, MS_COLS columns), in v_mfma_f64_16x16x4 tiles.  A workgroup owns
+// MS_ROWS = 32 output samples of one group and one RHS column; wave w holds
+// the 2 x 2 tiles of rows 0..31 and columns 32w .. 32w+31 (tiles past the
+// group's columns are skipped).  The filter block is staged in LDS (zeros
+// pad Q to whole tiles and K steps), B is read from the pattern array eight
+// K steps at a time, and the result goes through LDS to the epilogue:
+// upward, each child row is phased and the children of a parent are added
+// in Morton order; downward, the parent's pattern is phased as it is loaded
+// and the result is added to the child's incoming pattern.
+// Operand layout of v_mfma_f64_16x16x4 (64 lanes): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result register v of lane l is
+// D[l / 16 + 4 v][l % 16].
+// ---------------------------------------------------------------------------
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int MS_ROWS = 32;
+constexpr int MS_COLS = 128;
+constexpr int MS_MIN_ITEMS = 256;  // (group, row block) items per RHS column for the matrix-core path
+static_assert(SHIFT_GROUP * 10 <= MS_COLS, "shift group exceeds the GEMM columns");
+
+__host__ __device__ inline size_t mshift_smem(int Q) {
+  const int kp = (Q + 3) & ~3;
+  return (size_t)std::max(kp, MS_COLS) * MS_ROWS * sizeof(double);
+}
+
+// Fs[k][i] = table[k][q0 + i] (input sample k, output sample q0 + i), zero
+// outside the Q x Q table.
+__device__ __forceinline__ void mshift_stage(const double* __restrict__ tab, double* Fs, int Q, int q0) {
+  const int kp = (Q + 3) & ~3;
+  for (int e = threadIdx.x; e < kp * MS_ROWS; e += blockDim.x) {
+    const int k = e / MS_ROWS, i = e - k * MS_ROWS;
+    Fs[e] = k < Q && q0 + i < Q ? tab[(size_t)k * Q + q0 + i] : 0.0;
+  }
+}
+
+// acc[t][ct] += A_t B_ct over all K, A from Fs; B(ct, k) = value(ct, k,
+// fetch(ct, k)) for k < Q, 0 beyond.  fetch issues the (unconditional,
+// in-bounds) global loads; batches of KU K steps are double-buffered in
+// registers, so the next batch is in flight while this one is multiplied.
+// pre() stages Fs (and what else the epilogue needs) after the first batch
+// is issued.
+// col_ok[ct]: the wave's column tile ct holds some column of the group.
+template <int KU, typename T, typename FE, typename VA, typename PRE>
+__device__ __forceinline__ void mshift_gemm(const double* Fs, int Q, const bool (&col_ok)[2], FE fetch, VA value,
+                                            PRE pre, f64x4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, kq = lane >> 4, jl = lane & 15;
+  const int kp = (Q + 3) & ~3, kb = 4 * KU, nbat = (kp + kb - 1) / kb;
+  T b0[KU][2], b1[KU][2];
+  auto get = [&](T (&bv)[KU][2], int k0) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) bv[u][ct] = fetch(ct, min(k0 + 4 * u + kq, Q - 1));
+  };
+  auto mul = [&](const T (&bv)[KU][2], int k0) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      if (k0 + 4 * u >= kp) break;
+      const int k = k0 + 4 * u + kq;
+      const double a0 = Fs[k * MS_ROWS + jl], a1 = Fs[k * MS_ROWS + 16 + jl];
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+        if (col_ok[ct]) {
+          const double bb = k < Q ? value(ct, k, bv[u][ct]) : 0.0;
+          acc[0][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bb, acc[0][ct], 0, 0, 0);
+          acc[1][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bb, acc[1][ct], 0, 0, 0);
+        }
+    }
+  };
+  get(b0, 0);
+  pre();  // LDS staging, overlapped with the first batch's loads; ends in a barrier
+  for (int n = 0; n < nbat; n += 2) {
+    if (n + 1 < nbat) get(b1, (n + 1) * kb);
+    mul(b0, n * kb);
+    if (n + 1 >= nbat) break;
+    if (n + 2 < nbat) get(b0, (n + 2) * kb);
+    mul(b1, (n + 1) * kb);
+  }
+}
+
+// acc -> Ds[row][col] (the LDS of Fs, after every wave has left the GEMM)
+__device__ __forceinline__ void mshift_store(const f64x4 (&acc)[2][2], double* Ds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        Ds[(t * 16 + (lane >> 4) + 4 * v) * MS_COLS + w * 32 + ct * 16 + (lane & 15)] = acc[t][ct][v];
+}
+
+__global__ void __launch_bounds__(256) k_mshift_up(DevLevel Lp, DevLevel Lc, const cx<double>* __restrict__ Sc,
+                                                   cx<double>* __restrict__ Sp, const double* __restrict__ Ft,
+                                                   const cx<double>* __restrict__ ph, int Q, int R, int ntile) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* Fs = (double*)smem;
+  cx<double>* phs = (cx<double>*)(Fs + mshift_smem(Q) / sizeof(double));  // [child][row] output phases
+  int32_t* cps = (int32_t*)(phs + SHIFT_GROUP * MS_ROWS);                 // child ranges of the parents
+  ShiftItem it;
+  if (!shift_item(Lp.nug, ntile, R, MS_ROWS, it)) return;
+  const int q0 = it.q0, r = it.r;
+  const int nq = min(MS_ROWS, Q - q0);
+  const int p0 = Lp.ug_ptr[it.g], p1 = Lp.ug_ptr[it.g + 1];
+  const int c0 = Lp.child_ptr[p0], c1 = Lp.child_ptr[p1];
+  const int nch = c1 - c0, ncols = 10 * nch, np = p1 - p0;
+  const int w = threadIdx.x >> 6, jl = threadIdx.x & 15;
+  const double* S = (const double*)Sc;
+  size_t base[2];
+  bool col_ok[2], valid[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    const int cbase = w * 32 + ct * 16, col = cbase + jl;
+    col_ok[ct] = cbase < ncols;
+    valid[ct] = col < ncols;
+    const int ci = col / 10, rem = col - ci * 10;
+    base[ct] = valid[ct] ? (((size_t)(c0 + ci) * R + r) * Q) * 10 + rem : 0;
+  }
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+  mshift_gemm<8, double>(
+      Fs, Q, col_ok, [&](int ct, int k) { return S[base[ct] + (size_t)k * 10]; },
+      [&](int ct, int, double v) { return valid[ct] ? v : 0.0; },
+      [&] {
+        mshift_stage(Ft, Fs, Q, q0);
+        for (int e = threadIdx.x; e < nch * nq; e += blockDim.x) {
+          const int ci = e / nq, i = e - ci * nq;
+          phs[ci * MS_ROWS + i] = ph[(size_t)Lc.octant[c0 + ci] * Q + q0 + i];
+        }
+        for (int e = threadIdx.x; e <= np; e += blockDim.x) cps[e] = Lp.child_ptr[p0 + e] - c0;
+        __syncthreads();
+      },
+      acc);
+  __syncthreads();
+  mshift_store(acc, Fs);
+  __syncthreads();
+  const int m = np * nq * 5;
+  for (int e = threadIdx.x; e < m; e += blockDim.x) {
+    const int pl = e / (nq * 5), rem = e - pl * nq * 5;
+    const int i = rem / 5, kk = rem - i * 5;
+    cx<double> v = mk(0.0, 0.0);
+    for (int ci = cps[pl]; ci < cps[pl + 1]; ++ci) {
+      const double* d = Fs + i * MS_COLS + ci * 10 + 2 * kk;
+      v = v + phs[ci * MS_ROWS + i] * mk(d[0], d[1]);
+    }
+    Sp[(((size_t)(p0 + pl) * R + r) * Q + q0 + i) * 5 + kk] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mshift_down(DevLevel Lc, const cx<double>* __restrict__ Gp,
+                                                     cx<double>* __restrict__ Gc, const double* __restrict__ F,
+                                                     const cx<double>* __restrict__ ph, int Q, int R, int ntile) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* Fs = (double*)smem;
+  cx<double>* phs = (cx<double>*)(Fs + mshift_smem(Q) / sizeof(double));  // [8][Q] phases
+  const int ng = (Lc.nb + SHIFT_GROUP - 1) / SHIFT_GROUP;
+  ShiftItem it;
+  if (!shift_item(ng, ntile, R, MS_ROWS, it)) return;
+  const int q0 = it.q0, r = it.r;
+  const int nq = min(MS_ROWS, Q - q0);
+  const int c0 = it.g * SHIFT_GROUP, c1 = min(Lc.nb, c0 + SHIFT_GROUP);
+  const int ncols = 10 * (c1 - c0);
+  const int w = threadIdx.x >> 6, jl = threadIdx.x & 15;
+  const cx<double>* gp[2];
+  int po[2];
+  bool col_ok[2], valid[2], im[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    const int cbase = w * 32 + ct * 16, col = cbase + jl;
+    col_ok[ct] = cbase < ncols;
+    valid[ct] = col < ncols;
+    const int ci = col / 10, rem = col - ci * 10;
+    const int c = valid[ct] ? c0 + ci : c0;
+    gp[ct] = Gp + (((size_t)Lc.parent[c] * R + r) * Q) * 5 + (rem >> 1);
+    po[ct] = Lc.octant[c] * Q;
+    im[ct] = rem & 1;
+  }
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+  mshift_gemm<4, cx<double>>(
+      Fs, Q, col_ok, [&](int ct, int k) { return gp[ct][(size_t)k * 5]; },
+      [&](int ct, int k, const cx<double>& g) {
+        const cx<double> v = conj(phs[po[ct] + k]) * g;
+        return valid[ct] ? (im[ct] ? v.im : v.re) : 0.0;
+      },
+      [&] {
+        mshift_stage(F, Fs, Q, q0);
+        for (int e = threadIdx.x; e < 8 * Q; e += blockDim.x) phs[e] = ph[e];
+        __syncthreads();
+      },
+      acc);
+  __syncthreads();
+  mshift_store(acc, Fs);
+  __syncthreads();
+  const int m = (c1 - c0) * nq * 5;
+  for (int e = threadIdx.x; e < m; e += blockDim.x) {
+    const int ci = e / (nq * 5), rem = e - ci * nq * 5;
+    const int i = rem / 5, kk = rem - i * 5;
+    const double* d = Fs + i * MS_COLS + ci * 10 + 2 * kk;
+    cx<double>* o = Gc + (((size_t)(c0 + ci) * R + r) * Q + q0 + i) * 5 + kk;
+    *o = *o + mk(d[0], d[1]);
   }
 }
 
@@ -685,6 +898,16 @@ template <typename TF>
 hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* Sc, void* Sp, const void* Ft,
                            const void* ph, int Q, int R, hipStream_t st) {
   static_assert(SHIFT_GROUP * 5 <= SHIFT_LANES, "shift group exceeds its lanes");
+  // matrix cores when the level has enough groups to fill the device; the
+  // vector kernel (more, shorter work items) otherwise
+  if (sizeof(TF) == 8 && Lp.nug * ((Q + MS_ROWS - 1) / MS_ROWS) >= MS_MIN_ITEMS) {
+    const int ntile = (Q + MS_ROWS - 1) / MS_ROWS;
+    const unsigned grid = 8u * (unsigned)(((Lp.nug + 7) / 8) * ntile * R);
+    const size_t sm = mshift_smem(Q) + SHIFT_GROUP * MS_ROWS * sizeof(cx<double>) + (SHIFT_GROUP + 1) * sizeof(int32_t);
+    hipLaunchKernelGGL(k_mshift_up, dim3(grid), dim3(256), sm, st, Lp, Lc, (const cx<double>*)Sc,
+                       (cx<double>*)Sp, (const double*)Ft, (const cx<double>*)ph, Q, R, ntile);
+    return hipGetLastError();
+  }
   const int ntile = (Q + SQT - 1) / SQT;
   const unsigned grid = 8u * (unsigned)(((Lp.nug + 7) / 8) * ntile * R);
   hipLaunchKernelGGL(k_shift_up<TF>, dim3(grid), dim3(SHIFT_SLICES * SHIFT_LANES), shift_smem(Q, sizeof(TF)), st,
@@ -695,8 +918,16 @@ hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* S
 template <typename TF>
 hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const void* F, const void* ph, int Q,
                              int R, hipStream_t st) {
-  const int ntile = (Q + SQT - 1) / SQT;
   const int ng = (Lc.nb + SHIFT_GROUP - 1) / SHIFT_GROUP;
+  if (sizeof(TF) == 8 && ng * ((Q + MS_ROWS - 1) / MS_ROWS) >= MS_MIN_ITEMS) {
+    const int ntile = (Q + MS_ROWS - 1) / MS_ROWS;
+    const unsigned grid = 8u * (unsigned)(((ng + 7) / 8) * ntile * R);
+    hipLaunchKernelGGL(k_mshift_down, dim3(grid), dim3(256), mshift_smem(Q) + 8 * (size_t)Q * sizeof(cx<double>), st,
+                       Lc, (const cx<double>*)Gp,
+                       (cx<double>*)Gc, (const double*)F, (const cx<double>*)ph, Q, R, ntile);
+    return hipGetLastError();
+  }
+  const int ntile = (Q + SQT - 1) / SQT;
   const unsigned grid = 8u * (unsigned)(((ng + 7) / 8) * ntile * R);
   hipLaunchKernelGGL(k_shift_down<TF>, dim3(grid), dim3(SHIFT_SLICES * SHIFT_LANES), shift_smem(Q, sizeof(TF)),
                      st, Lc, (const cx<TF>*)Gp, (cx<TF>*)Gc, (const TF*)F, (const cx<TF>*)ph, Q, R, ntile);

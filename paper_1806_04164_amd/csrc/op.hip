@@ -1185,30 +1185,37 @@ pie_status pie_autotune(pie_op* op, const void* x, void* y, int64_t R, int32_t r
   pie_schedule best{1, op->sched_near, op->sched_il, op->sched_chunk};
   double best_ms = 1e300;
   s = PIE_OK;
-  for (int nf = PIE_NEAR_SERIAL; nf <= PIE_NEAR_FORK_AFTER_AGGREGATE && !s; ++nf)
-    for (int il = 0; il <= 2 && !s; ++il)
-      for (int ch : {4, 2, 1}) {
+  std::vector<pie_schedule> cand;
+  for (int nf = PIE_NEAR_SERIAL; nf <= PIE_NEAR_FORK_AFTER_AGGREGATE; ++nf)
+    for (int il = 0; il <= 2; ++il)
+      for (int ch : {4, 2, 1})
         // register groups wider than R or than the operator's limit repeat a narrower one
-        if (ch > 1 && (ch > op->rc || ch > R)) continue;
-        op->sched_near = nf;
-        op->sched_il = il;
-        op->sched_chunk = ch;
-        if ((s = mvm(op, x, y, R, 3, st))) break;
-        if (hipEventRecord(e0, st) != hipSuccess) { s = PIE_ERR_HIP; break; }
-        for (int i = 0; i < reps && !s; ++i) s = mvm(op, x, y, R, 3, st);
-        if (s) break;
-        float t = 0.0f;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
-          s = PIE_ERR_HIP;
-          break;
-        }
-        const double per = (double)t / reps;
-        if (per < best_ms) {
-          best_ms = per;
-          best = pie_schedule{1, nf, il, ch};
-        }
+        if (ch == 1 || (ch <= op->rc && ch <= R)) cand.push_back(pie_schedule{1, nf, il, ch});
+  // two rounds over the candidates, each keeping its faster round, so that
+  // the order of measurement does not favour any schedule
+  std::vector<double> t_ms(cand.size(), 1e300);
+  for (int round = 0; round < 2 && !s; ++round)
+    for (size_t c = 0; c < cand.size() && !s; ++c) {
+      op->sched_near = cand[c].near_fork;
+      op->sched_il = cand[c].il_fork;
+      op->sched_chunk = cand[c].max_chunk;
+      if ((s = mvm(op, x, y, R, 3, st))) break;
+      if (hipEventRecord(e0, st) != hipSuccess) { s = PIE_ERR_HIP; break; }
+      for (int i = 0; i < reps && !s; ++i) s = mvm(op, x, y, R, 3, st);
+      if (s) break;
+      float t = 0.0f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+        s = PIE_ERR_HIP;
+        break;
       }
+      t_ms[c] = std::min(t_ms[c], (double)t / reps);
+    }
+  for (size_t c = 0; c < cand.size(); ++c)
+    if (t_ms[c] < best_ms) {
+      best_ms = t_ms[c];
+      best = cand[c];
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   op->sched_near = best.near_fork;

@@ -220,7 +220,9 @@ pie_status pie_profile_read(pie_op* op, double* ms, int64_t* launches);
  *   il_fork: 0 keeps the finest level's interaction-list translation on
  *     the caller's stream; 1 runs it on a third stream forked after the
  *     aggregation (concurrent with the upward shifts); 2 forks it after
- *     the first upward shift (concurrent with the coarse levels).
+ *     the first upward shift (concurrent with the coarse levels); 3 runs
+ *     the translation of every level >= 4 on a stream of its own, forked
+ *     as soon as that level's patterns exist.
  *   max_chunk: widest register group of RHS columns inside a kernel (1, 2
  *     or 4; the operator's own limit from its LDS budget applies).
  * Default: PIE_NEAR_FORK_START, il_fork 1, max_chunk 4. */
@@ -234,7 +236,7 @@ typedef struct pie_schedule {
   int32_t max_chunk;
 } pie_schedule;
 pie_status pie_schedule_get(const pie_op* op, pie_schedule* out);
-/* PIE_ERR_ARG for an unknown near_fork, il_fork not 0, 1 or 2, or max_chunk not
+/* PIE_ERR_ARG for an unknown near_fork, il_fork not 0..3, or max_chunk not
  * 1, 2 or 4. */
 pie_status pie_schedule_set(pie_op* op, const pie_schedule* sch);
 

@@ -59,6 +59,10 @@ struct pie_op {
   // needs only the finest patterns and overlaps the upward shifts
   hipStream_t side2 = nullptr;
   hipEvent_t ev_agg = nullptr, ev_il = nullptr;
+  // one stream per level 4..L for translations forked as soon as the
+  // level's patterns exist (il_fork 3), with their fork and join events
+  std::vector<hipStream_t> il_st;
+  std::vector<hipEvent_t> ev_s, ev_g;
   // launch schedule (every choice gives the same result, bit for bit)
   int sched_near = PIE_NEAR_FORK_START;  // where the near field forks off the far chain
   int sched_il = 1;                      // finest translation on the third stream
@@ -95,6 +99,12 @@ struct pie_op {
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_agg) (void)hipEventDestroy(ev_agg);
     if (ev_il) (void)hipEventDestroy(ev_il);
+    for (hipStream_t x : il_st)
+      if (x) (void)hipStreamDestroy(x);
+    for (hipEvent_t x : ev_s)
+      if (x) (void)hipEventDestroy(x);
+    for (hipEvent_t x : ev_g)
+      if (x) (void)hipEventDestroy(x);
     for (auto& u : ev_used) {
       (void)hipEventDestroy(u.second.first);
       (void)hipEventDestroy(u.second.second);
@@ -795,8 +805,11 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
     // finest-level translation on the third stream, concurrent with the
     // upward shifts and the coarser translations; forked after the
     // aggregation (il_fork 1) or after the first upward shift (il_fork 2),
-    // so that it overlaps the small coarse-level kernels instead
-    const bool fork2 = L > 3 && op->sched_il;
+    // so that it overlaps the small coarse-level kernels instead.  il_fork 3
+    // forks every level >= 4 to its own stream as soon as its patterns
+    // exist and joins it before the downward shift into that level.
+    const bool perlev = L > 3 && op->sched_il == 3;
+    const bool fork2 = L > 3 && (op->sched_il == 1 || op->sched_il == 2);
     auto translate = [&](int l, hipStream_t s) {
       return stage(op, PIE_STAGE_TRANSLATE, s, [&] {
         return launch_translate<TF>(op->lv[l], op->dS[l], op->dTl[l], op->dG[l], Q, R, s);
@@ -809,6 +822,17 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
       HIPCHK(hipEventRecord(op->ev_il, op->side2), "join");
       return PIE_OK;
     };
+    auto fork_level = [&](int l) -> pie_status {
+      HIPCHK(hipEventRecord(op->ev_s[l], st), "fork");
+      HIPCHK(hipStreamWaitEvent(op->il_st[l], op->ev_s[l], 0), "fork");
+      if ((e = translate(l, op->il_st[l])) != hipSuccess) return hip_fail(e, "translate");
+      HIPCHK(hipEventRecord(op->ev_g[l], op->il_st[l]), "join");
+      return PIE_OK;
+    };
+    if (perlev) {
+      pie_status ps = fork_level(L);
+      if (ps) return ps;
+    }
     if (fork2 && op->sched_il == 1) {
       pie_status ps = fork_translate();
       if (ps) return ps;
@@ -823,12 +847,17 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
         pie_status ps = fork_translate();
         if (ps) return ps;
       }
+      if (perlev && l >= 4) {
+        pie_status ps = fork_level(l);
+        if (ps) return ps;
+      }
     }
     for (int l = 3; l <= L; ++l)
-      if (l < L || !fork2)
+      if (perlev ? l == 3 : (l < L || !fork2))
         if ((e = translate(l, st)) != hipSuccess) return hip_fail(e, "translate");
     for (int l = 4; l <= L; ++l) {
       if (l == L && fork2) HIPCHK(hipStreamWaitEvent(st, op->ev_il, 0), "join");
+      if (perlev) HIPCHK(hipStreamWaitEvent(st, op->ev_g[l], 0), "join");
       if ((e = stage(op, PIE_STAGE_SHIFT_DOWN, st, [&] {
              return launch_shift_down<TF>(op->lv[l], op->dG[l - 1], op->dG[l], op->dFl[l - 1], op->dPhl[l - 1],
                                           Q, R, st);
@@ -1078,6 +1107,14 @@ pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq
   HIPCHK(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming), "fork event");
   HIPCHK(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming), "join event");
   HIPCHK(hipStreamCreateWithFlags(&op->side2, hipStreamNonBlocking), "side stream");
+  op->il_st.assign(op->L + 1, nullptr);
+  op->ev_s.assign(op->L + 1, nullptr);
+  op->ev_g.assign(op->L + 1, nullptr);
+  for (int l = 4; l <= op->L; ++l) {
+    HIPCHK(hipStreamCreateWithFlags(&op->il_st[l], hipStreamNonBlocking), "level stream");
+    HIPCHK(hipEventCreateWithFlags(&op->ev_s[l], hipEventDisableTiming), "fork event");
+    HIPCHK(hipEventCreateWithFlags(&op->ev_g[l], hipEventDisableTiming), "join event");
+  }
   HIPCHK(hipEventCreateWithFlags(&op->ev_agg, hipEventDisableTiming), "fork event");
   HIPCHK(hipEventCreateWithFlags(&op->ev_il, hipEventDisableTiming), "join event");
   pie_status s = build_operator(op.get(), st);
@@ -1155,7 +1192,7 @@ pie_status pie_schedule_set(pie_op* op, const pie_schedule* sch) {
     return PIE_ERR_ARG;
   }
   if (sch->near_fork < PIE_NEAR_SERIAL || sch->near_fork > PIE_NEAR_FORK_AFTER_AGGREGATE ||
-      (sch->il_fork < 0 || sch->il_fork > 2) ||
+      (sch->il_fork < 0 || sch->il_fork > 3) ||
       (sch->max_chunk != 1 && sch->max_chunk != 2 && sch->max_chunk != 4)) {
     pie::set_error("invalid schedule");
     return PIE_ERR_ARG;
@@ -1187,7 +1224,7 @@ pie_status pie_autotune(pie_op* op, const void* x, void* y, int64_t R, int32_t r
   s = PIE_OK;
   std::vector<pie_schedule> cand;
   for (int nf = PIE_NEAR_SERIAL; nf <= PIE_NEAR_FORK_AFTER_AGGREGATE; ++nf)
-    for (int il = 0; il <= 2; ++il)
+    for (int il = 0; il <= 3; ++il)
       for (int ch : {4, 2, 1})
         // register groups wider than R or than the operator's limit repeat a narrower one
         if (ch == 1 || (ch <= op->rc && ch <= R)) cand.push_back(pie_schedule{1, nf, il, ch});

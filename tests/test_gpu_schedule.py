@@ -45,7 +45,7 @@ def test_schedules_bitwise_equal(s4, near, far):
     ref = op.matvec(x).cpu().numpy()
     refa = op.matvec(x, adjoint=True).cpu().numpy()
     for nf, il, ch in itertools.product((PIE_NEAR_SERIAL, PIE_NEAR_FORK_START, PIE_NEAR_FORK_AFTER_AGGREGATE),
-                                        (0, 1, 2), (1, 2, 4)):
+                                        (0, 1, 2, 3), (1, 2, 4)):
         op.schedule = dict(near_fork=nf, il_fork=il, max_chunk=ch)
         assert op.schedule == dict(near_fork=nf, il_fork=il, max_chunk=ch)
         y = op.matvec(x).cpu().numpy()
@@ -57,7 +57,7 @@ def test_schedules_bitwise_equal(s4, near, far):
 
 def test_schedule_validation(s4):
     op = _op(s4, max_rhs=1)
-    for bad in (dict(near_fork=3), dict(il_fork=3), dict(max_chunk=3)):
+    for bad in (dict(near_fork=3), dict(il_fork=4), dict(max_chunk=3)):
         with pytest.raises(PieError):
             op.schedule = bad
 
@@ -90,12 +90,17 @@ def test_graph_replays_match_eager(s4, adjoint):
         op.matvec(other)
         torch.cuda.synchronize()
     # a graph keeps the schedule it was captured with
-    op.schedule = dict(near_fork=PIE_NEAR_SERIAL, il_fork=0, max_chunk=1)
-    g2 = op.graph(x, y, adjoint=adjoint)
-    for rep in range(2):
-        g2.launch()
-        torch.cuda.synchronize()
-        assert np.array_equal(y.cpu().numpy(), ref), rep
+    for sch in (dict(near_fork=PIE_NEAR_SERIAL, il_fork=0, max_chunk=1),
+                dict(near_fork=PIE_NEAR_FORK_START, il_fork=3, max_chunk=1)):
+        op.schedule = sch
+        g2 = op.graph(x, y, adjoint=adjoint)
+        for rep in range(2):
+            y.zero_()
+            g2.launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(y.cpu().numpy(), ref), (sch, rep)
+            op.matvec(other)
+            torch.cuda.synchronize()
 
 
 def test_batch_graph_matches_each_object():

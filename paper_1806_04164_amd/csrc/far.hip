@@ -16,6 +16,8 @@
 
 namespace pie {
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));  // v_mfma_f64 accumulator
+
 // ---------------------------------------------------------------------------
 // Finest-level radiation patterns through per-incidence moments.  For a
 // (box, triangle) incidence j with quadrature points r_i, weights W_i and
@@ -211,6 +213,144 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
 }
 
 // ---------------------------------------------------------------------------
+// Batched FP64 aggregation on the matrix cores (W >= MA_COLS columns in a
+// pass, paired samples).  For a box and a block of MA_COLS columns the
+// patterns are complex GEMMs over the box's incidences j:
+//   S_Jc = M1c a + M0 (-b_c),  S_sigma = M0 xp,  S_u = M0 cu
+// (rows: the Qh stored samples s).  With A = M(s) = Ar + i Ai and the
+// coefficient B = Br + i Bi, the real products P1 = Ar Br, P2 = Ai Bi,
+// P3 = Ar Bi, P4 = Ai Br give S(s) = (P1 - P2, P3 + P4) and, since
+// M(anti s) = conj M(s), S(anti s) = (P1 + P2, P3 - P4): every moment feeds
+// two samples.  Wave w takes the row tiles w, w + 4, ...; a K step is four
+// incidences; the coefficients of MA_JC incidences at a time are formed in
+// LDS as in k_aggregate.  v_mfma_f64_16x16x4 operand layout as for the
+// shifts.
+// ---------------------------------------------------------------------------
+constexpr int MA_COLS = 16;  // columns per workgroup
+constexpr int MA_JC = 16;    // incidences per coefficient chunk (a multiple of 4)
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_maggregate(DevInc I, int nbox, const cx<double>* __restrict__ x, int ldx,
+                                                    const cx<double>* __restrict__ M,
+                                                    const int32_t* __restrict__ anti, int Q, int Qh, double w2e,
+                                                    int conjx, int W, cx<double>* __restrict__ S) {
+  __shared__ cx<double> cf[MA_JC][6][MA_COLS];  // a, -bx, -by, -bz, xp, cu
+  __shared__ int32_t pair[256];
+  const int b = xcd_box(blockIdx.x, nbox);
+  if (b < 0) return;
+  const int c0 = blockIdx.y * MA_COLS;
+  const int j0 = I.ptr[b], ni = I.ptr[b + 1] - j0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kq = lane >> 4, jl = lane & 15;
+  const bool paired = Qh < Q;
+  for (int q = Qh + threadIdx.x; q < Q; q += blockDim.x) pair[anti[q]] = q;
+  __syncthreads();
+  const int ntile = (Qh + 15) >> 4;
+  for (int rt0 = 0; rt0 < ntile; rt0 += 4) {
+    const int rt = rt0 + w;  // this wave's row tile (may be past the last one)
+    const int s = rt * 16 + jl;
+    const bool srow = rt < ntile && s < Qh;
+    f64x4 acc[5][4];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) acc[k][p] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int jc = 0; jc < ni; jc += MA_JC) {
+      const int nj = min(MA_JC, ni - jc);
+      __syncthreads();  // previous chunk's coefficients consumed
+      for (int e = threadIdx.x; e < MA_JC * MA_COLS; e += blockDim.x) {
+        const int jj = e / MA_COLS, r = e - jj * MA_COLS;
+        cx<double> v[6];
+        if (jj < nj && c0 + r < W) {
+          const size_t j = (size_t)(j0 + jc + jj);
+          cx<double> xv[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int xi = I.xc[4 * j + k];
+            xv[k] = xi >= 0 ? x[(size_t)xi * ldx + c0 + r] : mk(0.0, 0.0);
+            if (conjx) xv[k].im = -xv[k].im;
+          }
+          cx<double> a = mk(0.0, 0.0), bb[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)}, cu = mk(0.0, 0.0);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const double sv = I.rs[3 * j + k], dv = I.rd[3 * j + k];
+            a = a + sv * xv[k];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bb[c] = bb[c] + (sv * I.pv[9 * j + 3 * k + c]) * xv[k];
+            cu = cu + dv * xv[k];
+          }
+          cu = cu + w2e * xv[3];
+          v[0] = a;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) v[1 + c] = mk(-bb[c].re, -bb[c].im);
+          v[4] = xv[3];
+          v[5] = cu;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 6; ++t) v[t] = mk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < 6; ++t) cf[jj][t][r] = v[t];
+      }
+      __syncthreads();
+      if (rt < ntile) {
+        // moments of step k0 + 4 load while step k0 is multiplied
+        auto load_m = [&](int k0, cx<double>(&m)[4]) {
+          const int jj = k0 + kq;
+          const bool ok = srow && jj < nj;
+          const cx<double>* mp = M + ((size_t)(j0 + jc + (ok ? jj : 0)) * Qh + (ok ? s : 0)) * 4;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const cx<double> v = mp[t];
+            m[t] = ok ? v : mk(0.0, 0.0);
+          }
+        };
+        cx<double> mn[4];
+        load_m(0, mn);
+        for (int k0 = 0; k0 < nj; k0 += 4) {
+          const int jj = k0 + kq;
+          cx<double> m[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) m[t] = mn[t];
+          if (k0 + 4 < nj) load_m(k0 + 4, mn);
+          cx<double> bv[6];
+#pragma unroll
+          for (int t = 0; t < 6; ++t) bv[t] = cf[jj < MA_JC ? jj : 0][t][jl];
+          // (moment, coefficient, component): M1c a -> Jc; M0 (-b_c) -> Jc; M0 xp -> sigma; M0 cu -> u
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int mi = t < 3 ? 1 + t : 0, bi = t < 3 ? 0 : t - 2, k = t < 3 ? t : (t < 6 ? t - 3 : t - 3);
+            const cx<double> A = m[mi], B = bv[bi];
+            acc[k][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.re, B.re, acc[k][0], 0, 0, 0);
+            acc[k][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.im, B.im, acc[k][1], 0, 0, 0);
+            acc[k][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.re, B.im, acc[k][2], 0, 0, 0);
+            acc[k][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(A.im, B.re, acc[k][3], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // epilogue: lane holds rows s = 16 rt + kq + 4 v of column c0 + jl
+    const int r = c0 + jl;
+    if (rt < ntile && r < W) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int sv = rt * 16 + kq + 4 * v;
+        if (sv < Qh) {
+          cx<double>* o = S + (((size_t)b * W + r) * Q + sv) * 5;
+#pragma unroll
+          for (int k = 0; k < 5; ++k)
+            o[k] = mk(acc[k][0][v] - acc[k][1][v], acc[k][2][v] + acc[k][3][v]);
+          if (paired) {
+            cx<double>* o2 = S + (((size_t)b * W + r) * Q + pair[sv]) * 5;
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+              o2[k] = mk(acc[k][0][v] + acc[k][1][v], acc[k][2][v] - acc[k][3][v]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Inter-level shifts as small GEMMs.  A workgroup owns a group of at most
 // SHIFT_GROUP boxes and a tile of SQT sample rows.  Its filter rows are
 // staged once in LDS; a lane owns one (box, column) pair and accumulates its
@@ -396,7 +536,6 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result register v of lane l is
 // D[l / 16 + 4 v][l % 16].
 // ---------------------------------------------------------------------------
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int MS_ROWS = 32;
 constexpr int MS_COLS = 128;
 constexpr int MS_MIN_ITEMS = 256;  // (group, row block) items per RHS column for the matrix-core path
@@ -880,6 +1019,12 @@ hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, 
                             void* S, hipStream_t st) {
   if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
   if (nsplit * Qh > 256) return hipErrorInvalidValue;
+  if (sizeof(TF) == 8 && W >= MA_COLS && Q <= 256) {
+    hipLaunchKernelGGL(k_maggregate, dim3(xcd_grid(nb), (W + MA_COLS - 1) / MA_COLS), dim3(256), 0, st, I, nb,
+                       (const cx<double>*)x, ldx, (const cx<double>*)M, anti, Q, Qh, w2e, conjx, W,
+                       (cx<double>*)S);
+    return hipGetLastError();
+  }
   const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
 #define AGG(RC_)                                                                                               \
   hipLaunchKernelGGL((k_aggregate<TF, RC_>), dim3(xcd_grid(nb)), dim3(256),                                    \

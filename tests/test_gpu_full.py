@@ -93,11 +93,21 @@ def test_batched_workload_sampled_rows():
     errs = _block_errors(_gpu_blocks(op, x, rows, E), ref, rows, E)
     print("R=64", errs, op.schedule, flush=True)
     assert max(errs.values()) <= 1e-3
-    # every column equals its own single-column MVM bit for bit
+    # passes of 16 or more columns aggregate on the matrix cores: a column
+    # equals itself bit for bit in any such pass, and its single-column MVM
+    # (vector aggregation, another summation order) to FP64 rounding carried
+    # through the translations.  With every level scaled (kappa d = x = 0.05,
+    # tau = 7) the sampled translation amplifies rounding of the patterns by
+    # up to (2 tau + 1)!!/(2 x)^tau ~ 2e13; measured here ~4e-5 relative, an
+    # order below the diagonalisation's truncation error (~4e-4)
     y = _gpu_blocks(op, x, np.arange(N), E)["J"]
+    y16 = _gpu_blocks(op, x[:, 32:48].copy(), np.arange(N), E, use_graph=False)["J"]
+    assert np.array_equal(y[:, 32:48], y16)
     for r in (0, 37, 63):
         y1 = _gpu_blocks(op, x[:, r:r + 1].copy(), np.arange(N), E, use_graph=False)["J"]
-        assert np.array_equal(y[:, r], y1[:, 0])
+        d = np.linalg.norm(y[:, r] - y1[:, 0]) / np.linalg.norm(y1[:, 0])
+        print("column", r, "batched vs single", d, flush=True)
+        assert d < 2e-4
 
 
 def test_gradient_workload_finite_differences():

@@ -154,6 +154,33 @@ def test_multi_rhs_matches_columns(c1):
         assert np.max(np.abs(Y[:, r] - y[:, 0])) <= 1e-14 * np.max(np.abs(y))
 
 
+def test_batched_aggregation(c1):
+    """Passes of 16 or more columns aggregate on the FP64 matrix cores: each
+    column equals itself bit for bit in any pass of 16 or more columns,
+    agrees with its single-column MVM (vector aggregation, other summation
+    order) to FP64 rounding carried through the translation (which amplifies
+    it: at tau = 7, x = 0.05 the MVM is linear only to ~1e-8, so 1e-7), and
+    matches the oracle's MLFMA far field."""
+    R = 20
+    op = _op(c1, max_rhs=R)
+    X = synth.complex_gaussian(c1["prob"].N, R, 5)
+    for adj in (False, True):
+        mv = (lambda v: op.matvec(v, adjoint=True)) if adj else op.matvec_far
+        Y = host(mv(dev(X)))
+        Y16 = host(mv(dev(X[:, 2:18].copy())))
+        assert np.array_equal(Y[:, 2:18], Y16)
+        for r in (0, 7, 19):
+            y = host(mv(dev(X[:, r:r + 1].copy())))[:, 0]
+            d = np.linalg.norm(Y[:, r] - y) / np.linalg.norm(y)
+            print("batched vs single column", adj, r, d, flush=True)
+            assert d < 1e-7
+    M = mlfma.MLFMA(c1["prob"], 3, mlfma.Params(tau=7, x=0.05))
+    errs = block_errors(lambda v: host(op.matvec_far(dev(np.repeat(v[:, None], R, axis=1))))[:, 11],
+                        M.far, c1["x"], c1["E"])
+    print("batched far vs oracle", errs, flush=True)
+    assert max(errs.values()) < 2e-3
+
+
 def test_bitwise_repeatable(c1):
     op = _op(c1, near=PIE_FP32, far=PIE_FP32)
     x = dev(c1["x"])

@@ -981,6 +981,200 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched FP64 reception on the matrix cores (W >= MR_COLS columns in a
+// pass).  For a box and a block of MR_COLS columns the six sums per
+// incidence (A, B, Cs, Du as in k_receive) are complex GEMMs over the stored
+// samples s: with M(s) = Mr + i Mi and, per pattern component, the sums
+// Sg = G(s) + G(anti s) and Dg = G(s) - G(anti s) of the incoming pattern,
+//   conj M(s) G(s) + M(s) G(anti s) = (Mr Sg_r + Mi Dg_i) + i (Mr Sg_i - Mi Dg_r),
+// so every moment again serves both samples.  Rows are incidences (row tile
+// rt of 16), K steps four stored samples, the (Sg, Dg) of MR_KC samples at
+// a time are staged in LDS; with one or two row tiles the waves also split
+// the K steps and their partial sums are added through LDS in a fixed
+// order.  The per-unknown assembly, the near-field join and the output
+// permutation then run as in k_receive.
+// ---------------------------------------------------------------------------
+constexpr int MR_COLS = 16;
+constexpr int MR_KC = 16;  // stored samples per staged chunk (four K steps)
+constexpr int MR_MAXI = 64;  // incidences per box (four row tiles)
+
+// LDS: one region for the staged (Sg, Dg), then the K-split partial sums,
+// then the per-incidence sums; after it the antipode table and the slots.
+size_t mreceive_buf(int maxinc) {
+  const size_t sd = (size_t)MR_KC * 5 * MR_COLS * 2 * sizeof(cx<double>);
+  const size_t pa = (size_t)2 * 64 * 48 * sizeof(double);
+  const size_t rd = (size_t)maxinc * 6 * MR_COLS * sizeof(cx<double>);
+  return std::max(std::max(sd, pa), rd);
+}
+size_t mreceive_smem(int maxinc, int maxjoin, int Q) {
+  return mreceive_buf(maxinc) + (size_t)(maxjoin + Q) * sizeof(int32_t) + 16;
+}
+
+template <typename TN>
+__global__ void __launch_bounds__(256) k_mreceive(DevInc I, DevBasis B, DevNear NB, int nbox,
+                                                  const cx<double>* __restrict__ Gin, const cx<double>* __restrict__ M,
+                                                  const int32_t* __restrict__ anti, int Q, int Qh, size_t buf,
+                                                  const cx<TN>* __restrict__ part, int flags, int W,
+                                                  cx<double>* __restrict__ y, int ldy) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = xcd_box(blockIdx.x, nbox);
+  if (b < 0) return;
+  const int c0 = blockIdx.y * MR_COLS;
+  const int j0 = I.ptr[b], ni = I.ptr[b + 1] - j0;
+  const bool do_far = flags & 2, do_near = flags & 1, conj_out = flags & 4;
+  cx<double>* SD = (cx<double>*)smem;    // [MR_KC][5][MR_COLS][2]: Sg, Dg
+  double* pa = (double*)smem;            // [2][64][48] partial sums of the K split
+  cx<double>* red = (cx<double>*)smem;   // [ni][6][MR_COLS]
+  int32_t* pairt = (int32_t*)(smem + buf);  // [Q] antipode of each stored sample
+  int32_t* slots = pairt + Q;                 // near-field partial-sum slots
+  const double mu0 = 4.0e-7 * 3.14159265358979323846;
+  const int nrow = do_near ? NB.row_ptr[b + 1] - NB.row_ptr[b] : 0;
+  const int nslot = do_near ? nrow + NB.col_ptr[b + 1] - NB.col_ptr[b] : 0;
+  for (int e = threadIdx.x; e < nslot; e += blockDim.x)
+    slots[e] = e < nrow ? NB.prow[NB.row_ptr[b] + e] : NB.pcol[NB.col_blk[NB.col_ptr[b] + e - nrow]];
+  const bool paired = Qh < Q;
+  for (int q = Qh + threadIdx.x; q < Q; q += blockDim.x) pairt[anti[q]] = q;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kq = lane >> 4, jl = lane & 15;
+  const int nrt = (ni + 15) >> 4;  // <= MR_MAXI / 16 (host)
+  const int ksplit = nrt == 1 ? 4 : (nrt == 2 ? 2 : 1);
+  const int rt = nrt > 0 ? w % nrt : 0, kh = nrt > 0 ? w / nrt : 4;
+  const bool wact = do_far && nrt > 0 && kh < ksplit;
+  const int jrow = rt * 16 + jl;
+  f64x4 acc[6][2];
+#pragma unroll
+  for (int o = 0; o < 6; ++o) acc[o][0] = acc[o][1] = f64x4{0.0, 0.0, 0.0, 0.0};
+  if (do_far) {
+    for (int sc = 0; sc < Qh; sc += MR_KC) {
+      __syncthreads();  // previous chunk consumed (and pair table / slots written)
+      for (int e = threadIdx.x; e < MR_KC * 5 * MR_COLS; e += blockDim.x) {
+        const int si = e / (5 * MR_COLS), rem = e - si * (5 * MR_COLS), k = rem / MR_COLS, r = rem - k * MR_COLS;
+        const int sv = sc + si;
+        cx<double> a = mk(0.0, 0.0), c = mk(0.0, 0.0);
+        if (sv < Qh && c0 + r < W) {
+          const cx<double>* g = Gin + (((size_t)b * W + c0 + r) * Q) * 5 + k;
+          a = g[(size_t)sv * 5];
+          if (paired) c = g[(size_t)pairt[sv] * 5];
+        }
+        SD[((si * 5 + k) * MR_COLS + r) * 2] = a + c;
+        SD[((si * 5 + k) * MR_COLS + r) * 2 + 1] = a - c;
+      }
+      __syncthreads();
+      if (wact) {
+#pragma unroll
+        for (int t = 0; t < MR_KC / 4; ++t) {
+          if (t % ksplit != kh) continue;
+          const int si = 4 * t + kq, sv = sc + si;
+          const bool ok = sv < Qh && jrow < ni;
+          const cx<double>* mp = M + ((size_t)(j0 + (ok ? jrow : 0)) * Qh + (ok ? sv : 0)) * 4;
+          cx<double> m[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const cx<double> v = mp[u];
+            m[u] = ok ? v : mk(0.0, 0.0);
+          }
+          // (moment, component) -> output: M1c.G_Jc -> A; M0.G_Jc -> Bc; M0.G_sigma -> Cs; M0.G_u -> Du
+#pragma unroll
+          for (int pi = 0; pi < 8; ++pi) {
+            const int mi = pi < 3 ? 1 + pi : 0, k = pi < 3 ? pi : pi - 3, o = pi < 3 ? 0 : pi - 2;
+            const cx<double> sg = SD[((si * 5 + k) * MR_COLS + jl) * 2];
+            const cx<double> dg = SD[((si * 5 + k) * MR_COLS + jl) * 2 + 1];
+            acc[o][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[mi].re, sg.re, acc[o][0], 0, 0, 0);
+            acc[o][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[mi].im, dg.im, acc[o][0], 0, 0, 0);
+            acc[o][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[mi].re, sg.im, acc[o][1], 0, 0, 0);
+            acc[o][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[mi].im, -dg.re, acc[o][1], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // K-split partial sums, added to the kh = 0 waves in order of kh
+    for (int h = 1; h < ksplit; ++h) {
+      __syncthreads();
+      if (wact && kh == h) {
+        double* pp = pa + ((size_t)rt * 64 + lane) * 48;
+#pragma unroll
+        for (int o = 0; o < 6; ++o)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) pp[(o * 2 + c) * 4 + v] = acc[o][c][v];
+      }
+      __syncthreads();
+      if (wact && kh == 0) {
+        const double* pp = pa + ((size_t)rt * 64 + lane) * 48;
+#pragma unroll
+        for (int o = 0; o < 6; ++o)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[o][c][v] += pp[(o * 2 + c) * 4 + v];
+      }
+    }
+    __syncthreads();
+    if (wact && kh == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jr = rt * 16 + kq + 4 * v;
+        if (jr < ni)
+#pragma unroll
+          for (int o = 0; o < 6; ++o) red[((size_t)jr * 6 + o) * MR_COLS + jl] = mk(acc[o][0][v], acc[o][1][v]);
+      }
+    }
+  }
+  __syncthreads();
+  const int u0 = NB.box_ptr[b], nu = NB.box_ptr[b + 1] - u0;
+  for (int e = threadIdx.x; e < nu * MR_COLS; e += blockDim.x) {
+    const int ul = e / MR_COLS, r = e - ul * MR_COLS;
+    if (c0 + r >= W) continue;
+    const int u = u0 + ul;
+    const int cu = B.perm[u];
+    cx<double> val = mk(0.0, 0.0);
+    if (do_far) {
+      if (cu < B.ne) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const cx<double>* rv = red + (size_t)(I.uj[2 * u + h] - j0) * 6 * MR_COLS + r;
+          const double sv = I.us[2 * u + h], d = I.ud[2 * u + h];
+          cx<double> t = rv[0];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double pc = I.upv[6 * (size_t)u + 3 * h + c];
+            t.re -= pc * rv[(1 + c) * MR_COLS].re;
+            t.im -= pc * rv[(1 + c) * MR_COLS].im;
+          }
+          val.re += mu0 * sv * t.re + d * rv[4 * MR_COLS].re;
+          val.im += mu0 * sv * t.im + d * rv[4 * MR_COLS].im;
+        }
+      } else {
+        const cx<double>* rv = red + (size_t)(I.uj[2 * u] - j0) * 6 * MR_COLS + r;
+        val.re += rv[5 * MR_COLS].re;
+        val.im += rv[5 * MR_COLS].im;
+      }
+    }
+    if (do_near) {
+      const size_t col = (size_t)c0 + r;
+      int k = 0;
+      for (; k + 4 <= nslot; k += 4) {
+        cx<TN> v[4];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) v[tt] = part[((size_t)slots[k + tt] + ul) * W + col];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          val.re += (double)v[tt].re;
+          val.im += (double)v[tt].im;
+        }
+      }
+      for (; k < nslot; ++k) {
+        const cx<TN> v = part[((size_t)slots[k] + ul) * W + col];
+        val.re += (double)v.re;
+        val.im += (double)v.im;
+      }
+    }
+    if (conj_out) val.im = -val.im;
+    y[(size_t)cu * ldy + c0 + r] = val;
+  }
+}
+
 // Canonical FP64 x -> box-order x in near-field precision (conjugated for
 // the adjoint).
 template <typename TN>
@@ -1099,6 +1293,13 @@ hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB,
                           const void* Gin, const void* M, const int32_t* anti, int Q, int Qh, const void* part,
                           int W, int rc, int flags, void* y, int ldy, hipStream_t st) {
   if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
+  if (sizeof(TF) == 8 && W >= MR_COLS && maxinc <= MR_MAXI) {
+    const size_t buf = mreceive_buf(maxinc);
+    hipLaunchKernelGGL(k_mreceive<TN>, dim3(xcd_grid(nb), (W + MR_COLS - 1) / MR_COLS), dim3(256),
+                       mreceive_smem(maxinc, maxjoin, Q), st, I, B, NB, nb, (const cx<double>*)Gin,
+                       (const cx<double>*)M, anti, Q, Qh, buf, (const cx<TN>*)part, flags, W, (cx<double>*)y, ldy);
+    return hipGetLastError();
+  }
   const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
 #define REC(RC_)                                                                                            \
   hipLaunchKernelGGL((k_receive<TF, TN, RC_>), dim3(xcd_grid(nb)), dim3(256),                               \

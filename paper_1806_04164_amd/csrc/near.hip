@@ -384,6 +384,107 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched FP32 near field on the matrix cores (W >= NM_COLS columns in a
+// pass).  Same persistent panel stream as k_near_spmm; for each block of
+// NM_COLS right-hand-side columns the row part Z x_b and the column part
+// Z^T x_a are complex GEMMs in v_mfma_f32_16x16x4 tiles (four real products
+// per complex one): waves 0 and 1 take the row tiles of the panel, waves 2
+// and 3 its column tiles, both reading the panel and the staged x block
+// from LDS.  Operand layout of v_mfma_f32_16x16x4 (64 lanes): lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; result register v of
+// lane l is D[4 (l / 16) + v][l % 16].
+// ---------------------------------------------------------------------------
+typedef float f32x4m __attribute__((ext_vector_type(4)));  // v_mfma_f32 accumulator
+constexpr int NM_COLS = 16;
+
+__global__ void __launch_bounds__(256) k_near_mspmm(DevNear NB, const cx<float>* __restrict__ Z,
+                                                    const cx<float>* __restrict__ xb, int ldx,
+                                                    cx<float>* __restrict__ part, int W) {
+  constexpr int ZCAP = 2048;  // 16 KiB panel
+  constexpr int NV = ZCAP / 2 / 256;
+  __shared__ __align__(16) cx<float> Zs[ZCAP];
+  __shared__ cx<float> xa_s[128 * NM_COLS];
+  __shared__ cx<float> xb_s[128 * NM_COLS];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, kq = lane >> 4, jl = lane & 15;
+  const int ntask = NB.ntask;
+  const int32_t* TW = (const int32_t*)NB.tdesc;
+  f32x4 zr[NV];
+  cx<float> ztail = mk<float>(0, 0);
+  auto fetch = [&](const NearTaskDesc& t) {
+    const int cnt = t.nr * (t.nb | 1), nv = cnt / 2;
+    const f32x4* src = (const f32x4*)(Z + t.off);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (tid + 256 * v < nv) zr[v] = __builtin_nontemporal_load(src + tid + 256 * v);
+    if ((cnt & 1) && tid == 0) ztail = Z[t.off + cnt - 1];
+  };
+  int task = blockIdx.x;
+  if (task >= ntask) return;
+  NearTaskDesc t = near_desc(TW[(size_t)task * 8 + (tid & 7)]);
+  fetch(t);
+  int next = task + gridDim.x;
+  int32_t wn = TW[(size_t)min(next, ntask - 1) * 8 + (tid & 7)];
+  for (;;) {
+    const int ldz = t.nb | 1;
+    {
+      const int cnt = t.nr * ldz, nv = cnt / 2;
+      f32x4* dst = (f32x4*)Zs;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (tid + 256 * v < nv) dst[tid + 256 * v] = zr[v];
+      if ((cnt & 1) && tid == 0) Zs[cnt - 1] = ztail;
+    }
+    const bool more = next < ntask;
+    const NearTaskDesc tn = near_desc(wn);
+    if (more) fetch(tn);  // in flight while this panel is multiplied
+    const int next2 = next + gridDim.x;
+    wn = TW[(size_t)min(next2, ntask - 1) * 8 + (tid & 7)];
+    const bool offd = t.pcol >= 0;
+    for (int c0 = 0; c0 < W; c0 += NM_COLS) {
+      if (c0 > 0) __syncthreads();  // the previous block's x staging is consumed
+      for (int e = tid; e < 128 * NM_COLS; e += blockDim.x) {
+        const int k = e / NM_COLS, j = e - k * NM_COLS;
+        const bool cj = c0 + j < W;
+        xb_s[e] = k < t.nb && cj ? xb[(size_t)(t.v0 + k) * ldx + c0 + j] : mk<float>(0, 0);
+        xa_s[e] = offd && k < t.nr && cj ? xb[(size_t)(t.ua + k) * ldx + c0 + j] : mk<float>(0, 0);
+      }
+      __syncthreads();
+      // rows (w < 2): tiles of panel rows against x_b; columns (w >= 2):
+      // tiles of panel columns against x_a
+      const bool rows = w < 2;
+      const int nti = rows ? (t.nr + 15) >> 4 : (offd ? (t.nb + 15) >> 4 : 0);
+      const int nk = rows ? t.nb : t.nr;
+      const cx<float>* xs = rows ? xb_s : xa_s;
+      for (int ti = w & 1; ti < nti; ti += 2) {
+        f32x4m are = {0.f, 0.f, 0.f, 0.f}, aim = {0.f, 0.f, 0.f, 0.f};
+        const int i = ti * 16 + jl;  // panel row (rows) or column (columns) of this lane's A
+        const bool iok = i < (rows ? t.nr : t.nb);
+        for (int k0 = 0; k0 < nk; k0 += 4) {
+          const int k = k0 + kq;
+          const bool ok = iok && k < nk;
+          const cx<float> a = ok ? Zs[rows ? i * ldz + k : k * ldz + i] : mk<float>(0, 0);
+          const cx<float> bx = k < nk ? xs[k * NM_COLS + jl] : mk<float>(0, 0);
+          are = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, bx.re, are, 0, 0, 0);
+          are = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.im, bx.im, are, 0, 0, 0);
+          aim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, bx.im, aim, 0, 0, 0);
+          aim = __builtin_amdgcn_mfma_f32_16x16x4f32(a.im, bx.re, aim, 0, 0, 0);
+        }
+        const int base = rows ? t.prow : t.pcol, lim = rows ? t.nr : t.nb;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ii = ti * 16 + 4 * kq + v;
+          if (ii < lim && c0 + jl < W) part[((size_t)base + ii) * W + c0 + jl] = mk(are[v], aim[v]);
+        }
+      }
+    }
+    if (!more) break;
+    __syncthreads();  // every reader of Zs / x staging is done
+    t = tn;
+    next = next2;
+  }
+}
+
 // ------------------------------------------------------------- launchers --
 template <typename TN>
 hipError_t launch_near_fill(const DevGeo& G, const DevBasis& B, const DevNear& NB, void* out,
@@ -415,6 +516,20 @@ hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, in
                             hipStream_t st) {
   if (NB.ntask == 0) return hipSuccess;
   if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
+  if (sizeof(TN) == 4 && W >= NM_COLS) {
+    static int wgs = 0;
+    if (wgs == 0) {
+      int per_cu = 0, dev = 0, ncu = 0;
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_near_mspmm, 256, 0);
+      if (e == hipSuccess) e = hipGetDevice(&dev);
+      if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      wgs = std::max(1, per_cu) * std::max(1, ncu);
+    }
+    hipLaunchKernelGGL(k_near_mspmm, dim3(std::min(NB.ntask, wgs)), dim3(256), 0, st, NB, (const cx<float>*)Z,
+                       (const cx<float>*)xb, ldx, (cx<float>*)part, W);
+    return hipGetLastError();
+  }
   const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
   // persistent grid: as many workgroups as fit on the device at once
 #define NS(G_)                                                                                       \

@@ -154,6 +154,24 @@ def test_multi_rhs_matches_columns(c1):
         assert np.max(np.abs(Y[:, r] - y[:, 0])) <= 1e-14 * np.max(np.abs(y))
 
 
+def test_near_field_batched(c1):
+    """Passes of 16 or more columns run the FP32 near field on the matrix
+    cores: every column against the oracle's near-field product, and bit
+    for bit the same in any such pass."""
+    R = 20
+    op = _op(c1, near=PIE_FP32, max_rhs=R)
+    X = synth.complex_gaussian(c1["prob"].N, R, 6)
+    Y = host(op.matvec_near(dev(X)))
+    Y16 = host(op.matvec_near(dev(X[:, 3:19].copy())))
+    assert np.array_equal(Y[:, 3:19], Y16)
+    M = mlfma.MLFMA(c1["prob"], 3, mlfma.Params(tau=6, x=0.07))
+    for r in (0, 9, 19):
+        errs = block_errors(lambda v: host(op.matvec_near(dev(np.repeat(v[:, None], R, axis=1))))[:, r],
+                            M.near, X[:, r], c1["E"])
+        print("batched near", r, errs, flush=True)
+        assert max(errs.values()) < 1e-6
+
+
 def test_batched_aggregation(c1):
     """Passes of 16 or more columns aggregate on the FP64 matrix cores: each
     column equals itself bit for bit in any pass of 16 or more columns,

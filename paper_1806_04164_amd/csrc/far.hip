@@ -1273,6 +1273,94 @@ hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Batched translation (W >= TB_MIN_COLS columns in a pass) by sibling
+// groups.  The boxes of one parent (at most 8) share most of their
+// interaction-list sources (the union is 3.6-4.4 times smaller than the sum
+// of the lists on the sphere workloads).  A workgroup owns one sibling group
+// and TB_Q samples and walks the W columns: the translation factors of each
+// thread's entries are loaded once for all columns; per column the union's
+// patterns for the workgroup's samples are staged in LDS (the next column's
+// staging loads in flight while this column is summed), thread (box,
+// sample, split) adds the entries j = split (mod TB_SPLIT) of its box in
+// ascending union index, and the TB_SPLIT partial sums (adjacent lanes) are
+// added by a fixed butterfly.
+// ---------------------------------------------------------------------------
+constexpr int TB_MIN_COLS = 16;
+constexpr int TB_STAGE = (TB_UMAX * TB_Q * 5 + 255) / 256;  // staged values per thread
+
+template <typename TF>
+__global__ void __launch_bounds__(256) k_translate_batch(DevLevel Lv, const cx<TF>* __restrict__ S,
+                                                         const cx<TF>* __restrict__ T, cx<TF>* __restrict__ Gout,
+                                                         int Q, int W, int ntile) {
+  __shared__ cx<TF> Ss[TB_UMAX * TB_Q * 5];
+  __shared__ int32_t usrc[TB_UMAX];
+  const int it = xcd_box(blockIdx.x, Lv.nsg * ntile);
+  if (it < 0) return;
+  const int g = it / ntile, tile = it - g * ntile;
+  const int q0 = tile * TB_Q;
+  const int b0 = Lv.sg_ptr[g], nbg = Lv.sg_ptr[g + 1] - b0;
+  const int ug = Lv.su_ptr[g], nu = Lv.su_ptr[g + 1] - ug;  // <= TB_UMAX (host)
+  const int sp = threadIdx.x % TB_SPLIT, ql = (threadIdx.x / TB_SPLIT) % TB_Q;
+  const int d = threadIdx.x / (TB_SPLIT * TB_Q), q = q0 + ql;
+  const bool act = d < nbg && q < Q;
+  const int b = b0 + (d < nbg ? d : 0);
+  const int e0 = Lv.il_ptr[b], ne = act ? Lv.il_ptr[b + 1] - e0 : 0;
+  for (int e = threadIdx.x; e < nu; e += blockDim.x) usrc[e] = Lv.su_src[ug + e];
+  cx<TF> tv[TB_EMAX];
+  int uu[TB_EMAX];
+#pragma unroll
+  for (int i = 0; i < TB_EMAX; ++i) {
+    const int j = sp + i * TB_SPLIT;
+    const int e = e0 + (j < ne ? j : 0);
+    uu[i] = j < ne ? Lv.se_u[e] * (TB_Q * 5) + ql * 5 : 0;
+    tv[i] = j < ne ? T[(size_t)Lv.se_off[e] * Q + q] : mk<TF>(0, 0);
+  }
+  const int nst = nu * TB_Q * 5;
+  cx<TF> sreg[TB_STAGE];
+  auto stage_load = [&](int r) {
+#pragma unroll
+    for (int i = 0; i < TB_STAGE; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      const int su = e / (TB_Q * 5), rem = e - su * (TB_Q * 5), qq = rem / 5, k = rem - qq * 5;
+      sreg[i] = e < nst && q0 + qq < Q ? S[(((size_t)usrc[su] * W + r) * Q + q0 + qq) * 5 + k] : mk<TF>(0, 0);
+    }
+  };
+  __syncthreads();  // usrc
+  stage_load(0);
+  for (int r = 0; r < W; ++r) {
+    __syncthreads();  // the previous column is summed
+#pragma unroll
+    for (int i = 0; i < TB_STAGE; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e < nst) Ss[e] = sreg[i];
+    }
+    __syncthreads();
+    if (r + 1 < W) stage_load(r + 1);  // in flight during this column's sums
+    cx<TF> acc[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc[k] = mk<TF>(0, 0);
+#pragma unroll
+    for (int i = 0; i < TB_EMAX; ++i)
+      if (sp + i * TB_SPLIT < ne) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) cfma(acc[k], tv[i], Ss[uu[i] + k]);
+      }
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int h = 1; h < TB_SPLIT; h <<= 1) {
+        acc[k].re += __shfl_xor(acc[k].re, h);
+        acc[k].im += __shfl_xor(acc[k].im, h);
+      }
+    if (act && sp == 0) {
+      cx<TF>* o = Gout + (((size_t)b * W + r) * Q + q) * 5;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) o[k] = acc[k];
+    }
+  }
+}
+
 // Interaction-list split: Q lanes rounded to wavefronts (at most 256 per
 // pass) times nsplit list slices in a block of at most 512 threads.
 int translate_width(int Q) { return std::min(256, 64 * ((Q + 63) / 64)); }
@@ -1281,6 +1369,12 @@ int translate_split(int Q) { return std::min(8, 512 / translate_width(Q)); }
 template <typename TF>
 hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, void* Gout, int Q, int R,
                             hipStream_t st) {
+  if (R >= TB_MIN_COLS && Lv.sib_ok) {
+    const int ntile = (Q + TB_Q - 1) / TB_Q;
+    hipLaunchKernelGGL(k_translate_batch<TF>, dim3(xcd_grid(Lv.nsg * ntile)), dim3(256), 0, st, Lv,
+                       (const cx<TF>*)S, (const cx<TF>*)T, (cx<TF>*)Gout, Q, R, ntile);
+    return hipGetLastError();
+  }
   const int width = translate_width(Q), ns = translate_split(Q);
   const size_t sm = 2 * (IL_MAX + 3) * sizeof(int32_t) + (size_t)(ns - 1) * width * 5 * 2 * sizeof(TF) + 16;
   hipLaunchKernelGGL(k_translate<TF>, dim3(xcd_grid(Lv.nb), R), dim3(width * ns), sm, st, Lv, (const cx<TF>*)S,

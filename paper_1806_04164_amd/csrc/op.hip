@@ -534,6 +534,49 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     dl.il_off = dilo;
     dl.nug = nug;
     dl.ug_ptr = dug;
+    {
+      // sibling groups: runs of boxes with one parent (children are
+      // contiguous in Morton order), the ascending union of their sources,
+      // and each box's entries reordered by union index
+      std::vector<int32_t> sg{0}, su{0}, usrc, seu(lvh.il_src.size()), seo(lvh.il_src.size());
+      bool ok = true;
+      for (int b = 1; b <= nb; ++b)
+        if (b == nb || lvh.parent[b] != lvh.parent[b - 1]) sg.push_back(b);
+      for (size_t g = 0; g + 1 < sg.size(); ++g) {
+        std::vector<int32_t> un;
+        for (int b = sg[g]; b < sg[g + 1]; ++b)
+          for (int64_t e = lvh.il_ptr[b]; e < lvh.il_ptr[b + 1]; ++e) un.push_back((int32_t)lvh.il_src[e]);
+        std::sort(un.begin(), un.end());
+        un.erase(std::unique(un.begin(), un.end()), un.end());
+        ok = ok && un.size() <= (size_t)TB_UMAX && sg[g + 1] - sg[g] <= 8;
+        for (int b = sg[g]; b < sg[g + 1]; ++b) {
+          const int64_t e0 = lvh.il_ptr[b], e1 = lvh.il_ptr[b + 1];
+          ok = ok && e1 - e0 <= (int64_t)TB_SPLIT * TB_EMAX;
+          std::vector<std::pair<int32_t, int32_t>> ent;
+          for (int64_t e = e0; e < e1; ++e)
+            ent.push_back({(int32_t)(std::lower_bound(un.begin(), un.end(), (int32_t)lvh.il_src[e]) - un.begin()),
+                           (int32_t)lvh.il_off[e]});
+          std::sort(ent.begin(), ent.end());
+          for (size_t i = 0; i < ent.size(); ++i) {
+            seu[e0 + i] = ent[i].first;
+            seo[e0 + i] = ent[i].second;
+          }
+        }
+        usrc.insert(usrc.end(), un.begin(), un.end());
+        su.push_back((int32_t)usrc.size());
+      }
+      int32_t *dsg, *dsu, *dusrc, *dseu, *dseo;
+      if ((s = upload(op, &dsg, sg)) || (s = upload(op, &dsu, su)) || (s = upload(op, &dusrc, usrc)) ||
+          (s = upload(op, &dseu, seu)) || (s = upload(op, &dseo, seo)))
+        return s;
+      dl.nsg = (int32_t)sg.size() - 1;
+      dl.sg_ptr = dsg;
+      dl.su_ptr = dsu;
+      dl.su_src = dusrc;
+      dl.se_u = dseu;
+      dl.se_off = dseo;
+      dl.sib_ok = ok;
+    }
     op->lv[l] = dl;
     op->il_pairs += (int64_t)lvh.il_src.size();
   }

@@ -51,16 +51,6 @@ __device__ __forceinline__ void cfma_conj(cx<T>& a, cx<T> b, cx<T> c) {
   a.im = fma(b.re, c.im, a.im);
   a.im = fma(-b.im, c.re, a.im);
 }
-template <typename T>
-__device__ __forceinline__ void sincos_t(T x, T* s, T* c);
-template <>
-__device__ __forceinline__ void sincos_t<float>(float x, float* s, float* c) {
-  sincosf(x, s, c);
-}
-template <>
-__device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c) {
-  sincos(x, s, c);
-}
 
 // Workgroup -> box index with consecutive boxes (Morton order, i.e. spatial
 // neighbours) on the same XCD: workgroups are dispatched round-robin over

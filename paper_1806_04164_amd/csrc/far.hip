@@ -538,7 +538,7 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
 // ---------------------------------------------------------------------------
 constexpr int MS_ROWS = 32;
 constexpr int MS_COLS = 128;
-constexpr int MS_MIN_ITEMS = 256;  // (group, row block) items per RHS column for the matrix-core path
+constexpr int MS_MIN_ITEMS = 256;  // (group, row block) items for the matrix-core path
 static_assert(SHIFT_GROUP * 10 <= MS_COLS, "shift group exceeds the GEMM columns");
 
 __host__ __device__ inline size_t mshift_smem(int Q) {
@@ -1237,9 +1237,11 @@ template <typename TF>
 hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* Sc, void* Sp, const void* Ft,
                            const void* ph, int Q, int R, hipStream_t st) {
   static_assert(SHIFT_GROUP * 5 <= SHIFT_LANES, "shift group exceeds its lanes");
-  // matrix cores when the level has enough groups to fill the device; the
-  // vector kernel (more, shorter work items) otherwise
-  if (sizeof(TF) == 8 && Lp.nug * ((Q + MS_ROWS - 1) / MS_ROWS) >= MS_MIN_ITEMS) {
+  // matrix cores when the level has enough (group, row block) items to fill
+  // the device, counting 16 columns for batched passes (so that the choice
+  // is the same for every batched pass width); the vector kernel (more,
+  // shorter work items) otherwise
+  if (sizeof(TF) == 8 && Lp.nug * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS) {
     const int ntile = (Q + MS_ROWS - 1) / MS_ROWS;
     const unsigned grid = 8u * (unsigned)(((Lp.nug + 7) / 8) * ntile * R);
     const size_t sm = mshift_smem(Q) + SHIFT_GROUP * MS_ROWS * sizeof(cx<double>) + (SHIFT_GROUP + 1) * sizeof(int32_t);
@@ -1258,7 +1260,7 @@ template <typename TF>
 hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const void* F, const void* ph, int Q,
                              int R, hipStream_t st) {
   const int ng = (Lc.nb + SHIFT_GROUP - 1) / SHIFT_GROUP;
-  if (sizeof(TF) == 8 && ng * ((Q + MS_ROWS - 1) / MS_ROWS) >= MS_MIN_ITEMS) {
+  if (sizeof(TF) == 8 && ng * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS) {
     const int ntile = (Q + MS_ROWS - 1) / MS_ROWS;
     const unsigned grid = 8u * (unsigned)(((ng + 7) / 8) * ntile * R);
     hipLaunchKernelGGL(k_mshift_down, dim3(grid), dim3(256), mshift_smem(Q) + 8 * (size_t)Q * sizeof(cx<double>), st,

@@ -539,6 +539,7 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
 constexpr int MS_ROWS = 32;
 constexpr int MS_COLS = 128;
 constexpr int MS_MIN_ITEMS = 256;  // (group, row block) items for the matrix-core path
+constexpr int MS_RCH = 8;          // RHS columns per workgroup (the filter block is staged once for them)
 static_assert(SHIFT_GROUP * 10 <= MS_COLS, "shift group exceeds the GEMM columns");
 
 __host__ __device__ inline size_t mshift_smem(int Q) {
@@ -601,7 +602,7 @@ __device__ __forceinline__ void mshift_gemm(const double* Fs, int Q, const bool 
   }
 }
 
-// acc -> Ds[row][col] (the LDS of Fs, after every wave has left the GEMM)
+// acc -> Ds[row][col]
 __device__ __forceinline__ void mshift_store(const f64x4 (&acc)[2][2], double* Ds) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -615,119 +616,131 @@ __device__ __forceinline__ void mshift_store(const f64x4 (&acc)[2][2], double* D
 
 __global__ void __launch_bounds__(256) k_mshift_up(DevLevel Lp, DevLevel Lc, const cx<double>* __restrict__ Sc,
                                                    cx<double>* __restrict__ Sp, const double* __restrict__ Ft,
-                                                   const cx<double>* __restrict__ ph, int Q, int R, int ntile) {
+                                                   const cx<double>* __restrict__ ph, int Q, int R, int ntile,
+                                                   int nchunk) {
   extern __shared__ __align__(16) unsigned char smem[];
-  double* Fs = (double*)smem;
-  cx<double>* phs = (cx<double>*)(Fs + mshift_smem(Q) / sizeof(double));  // [child][row] output phases
-  int32_t* cps = (int32_t*)(phs + SHIFT_GROUP * MS_ROWS);                 // child ranges of the parents
+  double* Fs = (double*)smem;                                            // filter block
+  double* Ds = Fs + mshift_smem(Q) / sizeof(double);                     // [MS_ROWS][MS_COLS] result
+  cx<double>* phs = (cx<double>*)(Ds + MS_ROWS * MS_COLS);               // [child][row] output phases
+  int32_t* cps = (int32_t*)(phs + SHIFT_GROUP * MS_ROWS);                // child ranges of the parents
   ShiftItem it;
-  if (!shift_item(Lp.nug, ntile, R, MS_ROWS, it)) return;
-  const int q0 = it.q0, r = it.r;
+  if (!shift_item(Lp.nug, ntile, nchunk, MS_ROWS, it)) return;
+  const int q0 = it.q0;
   const int nq = min(MS_ROWS, Q - q0);
   const int p0 = Lp.ug_ptr[it.g], p1 = Lp.ug_ptr[it.g + 1];
   const int c0 = Lp.child_ptr[p0], c1 = Lp.child_ptr[p1];
   const int nch = c1 - c0, ncols = 10 * nch, np = p1 - p0;
   const int w = threadIdx.x >> 6, jl = threadIdx.x & 15;
   const double* S = (const double*)Sc;
-  size_t base[2];
-  bool col_ok[2], valid[2];
+  const int r0 = it.r * MS_RCH, r1 = min(R, r0 + MS_RCH);
+  for (int r = r0; r < r1; ++r) {
+    size_t base[2];
+    bool col_ok[2], valid[2];
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct) {
-    const int cbase = w * 32 + ct * 16, col = cbase + jl;
-    col_ok[ct] = cbase < ncols;
-    valid[ct] = col < ncols;
-    const int ci = col / 10, rem = col - ci * 10;
-    base[ct] = valid[ct] ? (((size_t)(c0 + ci) * R + r) * Q) * 10 + rem : 0;
-  }
-  f64x4 acc[2][2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
-  mshift_gemm<8, double>(
-      Fs, Q, col_ok, [&](int ct, int k) { return S[base[ct] + (size_t)k * 10]; },
-      [&](int ct, int, double v) { return valid[ct] ? v : 0.0; },
-      [&] {
-        mshift_stage(Ft, Fs, Q, q0);
-        for (int e = threadIdx.x; e < nch * nq; e += blockDim.x) {
-          const int ci = e / nq, i = e - ci * nq;
-          phs[ci * MS_ROWS + i] = ph[(size_t)Lc.octant[c0 + ci] * Q + q0 + i];
-        }
-        for (int e = threadIdx.x; e <= np; e += blockDim.x) cps[e] = Lp.child_ptr[p0 + e] - c0;
-        __syncthreads();
-      },
-      acc);
-  __syncthreads();
-  mshift_store(acc, Fs);
-  __syncthreads();
-  const int m = np * nq * 5;
-  for (int e = threadIdx.x; e < m; e += blockDim.x) {
-    const int pl = e / (nq * 5), rem = e - pl * nq * 5;
-    const int i = rem / 5, kk = rem - i * 5;
-    cx<double> v = mk(0.0, 0.0);
-    for (int ci = cps[pl]; ci < cps[pl + 1]; ++ci) {
-      const double* d = Fs + i * MS_COLS + ci * 10 + 2 * kk;
-      v = v + phs[ci * MS_ROWS + i] * mk(d[0], d[1]);
+    for (int ct = 0; ct < 2; ++ct) {
+      const int cbase = w * 32 + ct * 16, col = cbase + jl;
+      col_ok[ct] = cbase < ncols;
+      valid[ct] = col < ncols;
+      const int ci = col / 10, rem = col - ci * 10;
+      base[ct] = valid[ct] ? (((size_t)(c0 + ci) * R + r) * Q) * 10 + rem : 0;
     }
-    Sp[(((size_t)(p0 + pl) * R + r) * Q + q0 + i) * 5 + kk] = v;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+    mshift_gemm<8, double>(
+        Fs, Q, col_ok, [&](int ct, int k) { return S[base[ct] + (size_t)k * 10]; },
+        [&](int ct, int, double v) { return valid[ct] ? v : 0.0; },
+        [&] {
+          if (r == r0) {  // the filter block, phases and child ranges, once for all columns
+            mshift_stage(Ft, Fs, Q, q0);
+            for (int e = threadIdx.x; e < nch * nq; e += blockDim.x) {
+              const int ci = e / nq, i = e - ci * nq;
+              phs[ci * MS_ROWS + i] = ph[(size_t)Lc.octant[c0 + ci] * Q + q0 + i];
+            }
+            for (int e = threadIdx.x; e <= np; e += blockDim.x) cps[e] = Lp.child_ptr[p0 + e] - c0;
+          }
+          __syncthreads();  // also: the previous column's result is consumed
+        },
+        acc);
+    mshift_store(acc, Ds);
+    __syncthreads();
+    const int m = np * nq * 5;
+    for (int e = threadIdx.x; e < m; e += blockDim.x) {
+      const int pl = e / (nq * 5), rem = e - pl * nq * 5;
+      const int i = rem / 5, kk = rem - i * 5;
+      cx<double> v = mk(0.0, 0.0);
+      for (int ci = cps[pl]; ci < cps[pl + 1]; ++ci) {
+        const double* d = Ds + i * MS_COLS + ci * 10 + 2 * kk;
+        v = v + phs[ci * MS_ROWS + i] * mk(d[0], d[1]);
+      }
+      Sp[(((size_t)(p0 + pl) * R + r) * Q + q0 + i) * 5 + kk] = v;
+    }
   }
 }
 
 __global__ void __launch_bounds__(256) k_mshift_down(DevLevel Lc, const cx<double>* __restrict__ Gp,
                                                      cx<double>* __restrict__ Gc, const double* __restrict__ F,
-                                                     const cx<double>* __restrict__ ph, int Q, int R, int ntile) {
+                                                     const cx<double>* __restrict__ ph, int Q, int R, int ntile,
+                                                     int nchunk) {
   extern __shared__ __align__(16) unsigned char smem[];
-  double* Fs = (double*)smem;
-  cx<double>* phs = (cx<double>*)(Fs + mshift_smem(Q) / sizeof(double));  // [8][Q] phases
+  double* Fs = (double*)smem;                                 // filter block
+  double* Ds = Fs + mshift_smem(Q) / sizeof(double);          // [MS_ROWS][MS_COLS] result
+  cx<double>* phs = (cx<double>*)(Ds + MS_ROWS * MS_COLS);    // [8][Q] phases
   const int ng = (Lc.nb + SHIFT_GROUP - 1) / SHIFT_GROUP;
   ShiftItem it;
-  if (!shift_item(ng, ntile, R, MS_ROWS, it)) return;
-  const int q0 = it.q0, r = it.r;
+  if (!shift_item(ng, ntile, nchunk, MS_ROWS, it)) return;
+  const int q0 = it.q0;
   const int nq = min(MS_ROWS, Q - q0);
   const int c0 = it.g * SHIFT_GROUP, c1 = min(Lc.nb, c0 + SHIFT_GROUP);
   const int ncols = 10 * (c1 - c0);
   const int w = threadIdx.x >> 6, jl = threadIdx.x & 15;
-  const cx<double>* gp[2];
-  int po[2];
-  bool col_ok[2], valid[2], im[2];
+  const int r0 = it.r * MS_RCH, r1 = min(R, r0 + MS_RCH);
+  for (int r = r0; r < r1; ++r) {
+    const cx<double>* gp[2];
+    int po[2];
+    bool col_ok[2], valid[2], im[2];
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct) {
-    const int cbase = w * 32 + ct * 16, col = cbase + jl;
-    col_ok[ct] = cbase < ncols;
-    valid[ct] = col < ncols;
-    const int ci = col / 10, rem = col - ci * 10;
-    const int c = valid[ct] ? c0 + ci : c0;
-    gp[ct] = Gp + (((size_t)Lc.parent[c] * R + r) * Q) * 5 + (rem >> 1);
-    po[ct] = Lc.octant[c] * Q;
-    im[ct] = rem & 1;
-  }
-  f64x4 acc[2][2];
+    for (int ct = 0; ct < 2; ++ct) {
+      const int cbase = w * 32 + ct * 16, col = cbase + jl;
+      col_ok[ct] = cbase < ncols;
+      valid[ct] = col < ncols;
+      const int ci = col / 10, rem = col - ci * 10;
+      const int c = valid[ct] ? c0 + ci : c0;
+      gp[ct] = Gp + (((size_t)Lc.parent[c] * R + r) * Q) * 5 + (rem >> 1);
+      po[ct] = Lc.octant[c] * Q;
+      im[ct] = rem & 1;
+    }
+    f64x4 acc[2][2];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
-  mshift_gemm<4, cx<double>>(
-      Fs, Q, col_ok, [&](int ct, int k) { return gp[ct][(size_t)k * 5]; },
-      [&](int ct, int k, const cx<double>& g) {
-        const cx<double> v = conj(phs[po[ct] + k]) * g;
-        return valid[ct] ? (im[ct] ? v.im : v.re) : 0.0;
-      },
-      [&] {
-        mshift_stage(F, Fs, Q, q0);
-        for (int e = threadIdx.x; e < 8 * Q; e += blockDim.x) phs[e] = ph[e];
-        __syncthreads();
-      },
-      acc);
-  __syncthreads();
-  mshift_store(acc, Fs);
-  __syncthreads();
-  const int m = (c1 - c0) * nq * 5;
-  for (int e = threadIdx.x; e < m; e += blockDim.x) {
-    const int ci = e / (nq * 5), rem = e - ci * nq * 5;
-    const int i = rem / 5, kk = rem - i * 5;
-    const double* d = Fs + i * MS_COLS + ci * 10 + 2 * kk;
-    cx<double>* o = Gc + (((size_t)(c0 + ci) * R + r) * Q + q0 + i) * 5 + kk;
-    *o = *o + mk(d[0], d[1]);
+      for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+    mshift_gemm<4, cx<double>>(
+        Fs, Q, col_ok, [&](int ct, int k) { return gp[ct][(size_t)k * 5]; },
+        [&](int ct, int k, const cx<double>& g) {
+          const cx<double> v = conj(phs[po[ct] + k]) * g;
+          return valid[ct] ? (im[ct] ? v.im : v.re) : 0.0;
+        },
+        [&] {
+          if (r == r0) {  // the filter block and phases, once for all columns
+            mshift_stage(F, Fs, Q, q0);
+            for (int e = threadIdx.x; e < 8 * Q; e += blockDim.x) phs[e] = ph[e];
+          }
+          __syncthreads();  // also: the previous column's result is consumed
+        },
+        acc);
+    mshift_store(acc, Ds);
+    __syncthreads();
+    const int m = (c1 - c0) * nq * 5;
+    for (int e = threadIdx.x; e < m; e += blockDim.x) {
+      const int ci = e / (nq * 5), rem = e - ci * nq * 5;
+      const int i = rem / 5, kk = rem - i * 5;
+      const double* d = Ds + i * MS_COLS + ci * 10 + 2 * kk;
+      cx<double>* o = Gc + (((size_t)(c0 + ci) * R + r) * Q + q0 + i) * 5 + kk;
+      *o = *o + mk(d[0], d[1]);
+    }
   }
 }
 
@@ -1242,11 +1255,12 @@ hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* S
   // is the same for every batched pass width); the vector kernel (more,
   // shorter work items) otherwise
   if (sizeof(TF) == 8 && Lp.nug * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS) {
-    const int ntile = (Q + MS_ROWS - 1) / MS_ROWS;
-    const unsigned grid = 8u * (unsigned)(((Lp.nug + 7) / 8) * ntile * R);
-    const size_t sm = mshift_smem(Q) + SHIFT_GROUP * MS_ROWS * sizeof(cx<double>) + (SHIFT_GROUP + 1) * sizeof(int32_t);
+    const int ntile = (Q + MS_ROWS - 1) / MS_ROWS, nchunk = (R + MS_RCH - 1) / MS_RCH;
+    const unsigned grid = 8u * (unsigned)(((Lp.nug + 7) / 8) * ntile * nchunk);
+    const size_t sm = mshift_smem(Q) + MS_ROWS * MS_COLS * sizeof(double) +
+                      SHIFT_GROUP * MS_ROWS * sizeof(cx<double>) + (SHIFT_GROUP + 1) * sizeof(int32_t);
     hipLaunchKernelGGL(k_mshift_up, dim3(grid), dim3(256), sm, st, Lp, Lc, (const cx<double>*)Sc,
-                       (cx<double>*)Sp, (const double*)Ft, (const cx<double>*)ph, Q, R, ntile);
+                       (cx<double>*)Sp, (const double*)Ft, (const cx<double>*)ph, Q, R, ntile, nchunk);
     return hipGetLastError();
   }
   const int ntile = (Q + SQT - 1) / SQT;
@@ -1261,11 +1275,11 @@ hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const
                              int R, hipStream_t st) {
   const int ng = (Lc.nb + SHIFT_GROUP - 1) / SHIFT_GROUP;
   if (sizeof(TF) == 8 && ng * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS) {
-    const int ntile = (Q + MS_ROWS - 1) / MS_ROWS;
-    const unsigned grid = 8u * (unsigned)(((ng + 7) / 8) * ntile * R);
-    hipLaunchKernelGGL(k_mshift_down, dim3(grid), dim3(256), mshift_smem(Q) + 8 * (size_t)Q * sizeof(cx<double>), st,
-                       Lc, (const cx<double>*)Gp,
-                       (cx<double>*)Gc, (const double*)F, (const cx<double>*)ph, Q, R, ntile);
+    const int ntile = (Q + MS_ROWS - 1) / MS_ROWS, nchunk = (R + MS_RCH - 1) / MS_RCH;
+    const unsigned grid = 8u * (unsigned)(((ng + 7) / 8) * ntile * nchunk);
+    const size_t sm = mshift_smem(Q) + MS_ROWS * MS_COLS * sizeof(double) + 8 * (size_t)Q * sizeof(cx<double>);
+    hipLaunchKernelGGL(k_mshift_down, dim3(grid), dim3(256), sm, st, Lc, (const cx<double>*)Gp, (cx<double>*)Gc,
+                       (const double*)F, (const cx<double>*)ph, Q, R, ntile, nchunk);
     return hipGetLastError();
   }
   const int ntile = (Q + SQT - 1) / SQT;

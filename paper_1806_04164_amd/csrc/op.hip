@@ -331,8 +331,17 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
       entries += (int64_t)na * nb;
       prow.push_back((int32_t)slot);
       slot += na;
-      int rpp = std::min(128, zcap / ldz);
-      if (op->near_prec == PIE_FP32 && rpp > 1) rpp &= ~1;  // even row starts: 16-byte aligned panels
+      // one panel when the block fits, else the fewest equal panels (even
+      // row counts for FP32, so that panel starts stay 16-byte aligned)
+      const int cap = std::max(1, std::min(128, zcap / ldz));
+      int rpp = na;
+      if (na > cap) {
+        for (int npn = (na + cap - 1) / cap;; ++npn) {
+          rpp = (na + npn - 1) / npn;
+          if (op->near_prec == PIE_FP32 && (rpp & 1)) ++rpp;
+          if (rpp <= cap) break;
+        }
+      }
       for (int i0 = 0; i0 < na; i0 += rpp) {
         int tid_ = (int)tdesc.size();
         NearTaskDesc d;

@@ -486,6 +486,18 @@ __global__ void __launch_bounds__(256) k_near_mspmm(DevNear NB, const cx<float>*
 }
 
 // ------------------------------------------------------------- launchers --
+constexpr int kMaxDevices = 64;
+
+// Workgroups of 256 threads of `kernel` resident at once on device dev.
+static hipError_t resident_workgroups(const void* kernel, int dev, int& out) {
+  int per_cu = 0, ncu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  out = std::max(1, per_cu) * std::max(1, ncu);
+  return hipSuccess;
+}
+
 template <typename TN>
 hipError_t launch_near_fill(const DevGeo& G, const DevBasis& B, const DevNear& NB, void* out,
                             double k, double w2e, hipStream_t st) {
@@ -516,35 +528,28 @@ hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, in
                             hipStream_t st) {
   if (NB.ntask == 0) return hipSuccess;
   if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
+  // persistent grids: as many workgroups as fit on the current device at
+  // once (cached per kernel and device)
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
   if (sizeof(TN) == 4 && W >= NM_COLS) {
-    static int wgs = 0;
-    if (wgs == 0) {
-      int per_cu = 0, dev = 0, ncu = 0;
-      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_near_mspmm, 256, 0);
-      if (e == hipSuccess) e = hipGetDevice(&dev);
-      if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-      if (e != hipSuccess) return e;
-      wgs = std::max(1, per_cu) * std::max(1, ncu);
-    }
-    hipLaunchKernelGGL(k_near_mspmm, dim3(std::min(NB.ntask, wgs)), dim3(256), 0, st, NB, (const cx<float>*)Z,
-                       (const cx<float>*)xb, ldx, (cx<float>*)part, W);
+    static int wgs[kMaxDevices] = {};
+    if (wgs[dev] == 0 && (e = resident_workgroups((const void*)k_near_mspmm, dev, wgs[dev])) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_near_mspmm, dim3(std::min(NB.ntask, wgs[dev])), dim3(256), 0, st, NB,
+                       (const cx<float>*)Z, (const cx<float>*)xb, ldx, (cx<float>*)part, W);
     return hipGetLastError();
   }
   const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
-  // persistent grid: as many workgroups as fit on the device at once
-#define NS(G_)                                                                                       \
-  do {                                                                                               \
-    static int wgs = 0;                                                                              \
-    if (wgs == 0) {                                                                                  \
-      int per_cu = 0, dev = 0, ncu = 0;                                                              \
-      hipError_t e_ = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_near_spmm<TN, G_>, 256, 0); \
-      if (e_ == hipSuccess) e_ = hipGetDevice(&dev);                                                 \
-      if (e_ == hipSuccess) e_ = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev); \
-      if (e_ != hipSuccess) return e_;                                                               \
-      wgs = std::max(1, per_cu) * std::max(1, ncu);                                                  \
-    }                                                                                                \
-    hipLaunchKernelGGL((k_near_spmm<TN, G_>), dim3(std::min(NB.ntask, wgs)), dim3(256), 0, st, NB,   \
-                       (const cx<TN>*)Z, (const cx<TN>*)xb, ldx, (cx<TN>*)part, W);                  \
+#define NS(G_)                                                                                      \
+  do {                                                                                              \
+    static int wgs[kMaxDevices] = {};                                                               \
+    if (wgs[dev] == 0 &&                                                                            \
+        (e = resident_workgroups((const void*)k_near_spmm<TN, G_>, dev, wgs[dev])) != hipSuccess)   \
+      return e;                                                                                     \
+    hipLaunchKernelGGL((k_near_spmm<TN, G_>), dim3(std::min(NB.ntask, wgs[dev])), dim3(256), 0, st, NB, \
+                       (const cx<TN>*)Z, (const cx<TN>*)xb, ldx, (cx<TN>*)part, W);                 \
   } while (0)
   if (g == 1) NS(1); else if (g == 2) NS(2); else NS(4);
 #undef NS

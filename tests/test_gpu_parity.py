@@ -199,6 +199,19 @@ def test_batched_aggregation(c1):
     assert max(errs.values()) < 2e-3
 
 
+def test_fp32_operator_batched(c1):
+    """The FP32 operator in a batched pass (sibling-group translation in
+    FP32, FP32 matrix-core near field): a column against the oracle's
+    MLFMA with the same tau and x, as for one column."""
+    R = 20
+    op = _op(c1, near=PIE_FP32, far=PIE_FP32, max_rhs=R)
+    M = mlfma.MLFMA(c1["prob"], 3, mlfma.Params(tau=4, x=0.15))
+    errs = block_errors(lambda v: host(op.matvec(dev(np.repeat(v[:, None], R, axis=1))))[:, 13],
+                        M.matvec, c1["x"], c1["E"])
+    print("fp32 operator batched", errs, flush=True)
+    assert max(errs.values()) < 5e-3
+
+
 def test_bitwise_repeatable(c1):
     op = _op(c1, near=PIE_FP32, far=PIE_FP32)
     x = dev(c1["x"])

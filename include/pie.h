@@ -228,7 +228,8 @@ pie_status pie_profile_read(pie_op* op, double* ms, int64_t* launches);
  *     aggregation (concurrent with the upward shifts); 2 forks it after
  *     the first upward shift (concurrent with the coarse levels); 3 runs
  *     the translation of every level >= 4 on a stream of its own, forked
- *     as soon as that level's patterns exist.
+ *     as soon as that level's patterns exist; 4 runs the translations of
+ *     all levels in one launch after the upward pass (no stream fork).
  *   max_chunk: widest register group of RHS columns inside a kernel (1, 2
  *     or 4; the operator's own limit from its LDS budget applies).
  * Default: PIE_NEAR_FORK_START, il_fork 1, max_chunk 4. */
@@ -242,7 +243,7 @@ typedef struct pie_schedule {
   int32_t max_chunk;
 } pie_schedule;
 pie_status pie_schedule_get(const pie_op* op, pie_schedule* out);
-/* PIE_ERR_ARG for an unknown near_fork, il_fork not 0..3, or max_chunk not
+/* PIE_ERR_ARG for an unknown near_fork, il_fork not 0..4, or max_chunk not
  * 1, 2 or 4. */
 pie_status pie_schedule_set(pie_op* op, const pie_schedule* sch);
 

@@ -61,7 +61,7 @@ __device__ __forceinline__ int xcd_box(int w, int nb) {
   const int b = (w & 7) * per + (w >> 3);
   return b < nb ? b : -1;
 }
-__host__ __forceinline__ unsigned xcd_grid(int nb) { return 8u * (unsigned)((nb + 7) >> 3); }
+__host__ __device__ __forceinline__ unsigned xcd_grid(int nb) { return 8u * (unsigned)((nb + 7) >> 3); }
 
 // Geometry (FP64).
 struct DevGeo {

@@ -17,6 +17,7 @@
 namespace pie {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));  // v_mfma_f64 accumulator
+constexpr int TSET_MAX = 8;  // levels per multi-level translation launch
 
 // ---------------------------------------------------------------------------
 // Finest-level radiation patterns through per-incidence moments.  For a
@@ -753,17 +754,17 @@ __global__ void __launch_bounds__(256) k_mshift_down(DevLevel Lc, const cx<doubl
 // sums are added in a fixed order through LDS.  nsplit depends on Q only,
 // so every RHS column is summed in the same order.
 // ---------------------------------------------------------------------------
+// (the body takes its box slot bx and column r as arguments so that one
+// launch can serve several levels)
 template <typename TF>
-__global__ void __launch_bounds__(512) k_translate(DevLevel Lv, const cx<TF>* __restrict__ S,
-                                                   const cx<TF>* __restrict__ T, cx<TF>* __restrict__ Gout,
-                                                   int Q, int R, int nsplit) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void translate_body(const DevLevel& Lv, const cx<TF>* __restrict__ S,
+                                               const cx<TF>* __restrict__ T, cx<TF>* __restrict__ Gout, int Q,
+                                               int R, int nsplit, int bx, int r, unsigned char* smem) {
   int32_t* ils = (int32_t*)smem;                 // [IL_MAX + 3]
   int32_t* ilo = ils + (IL_MAX + 3);             // [IL_MAX + 3]
   cx<TF>* part = (cx<TF>*)(ilo + (IL_MAX + 3));  // [nsplit - 1][width][5]
-  const int b = xcd_box(blockIdx.x, Lv.nb);
+  const int b = xcd_box(bx, Lv.nb);
   if (b < 0) return;
-  const int r = blockIdx.y;
   const int ncol = 5 * R;
   const int n = Q * ncol;
   const int i0 = Lv.il_ptr[b], nil = Lv.il_ptr[b + 1] - i0;
@@ -819,6 +820,37 @@ __global__ void __launch_bounds__(512) k_translate(DevLevel Lv, const cx<TF>* __
     }
     __syncthreads();
   }
+}
+
+template <typename TF>
+__global__ void __launch_bounds__(512) k_translate(DevLevel Lv, const cx<TF>* __restrict__ S,
+                                                   const cx<TF>* __restrict__ T, cx<TF>* __restrict__ Gout,
+                                                   int Q, int R, int nsplit) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  translate_body<TF>(Lv, S, T, Gout, Q, R, nsplit, blockIdx.x, blockIdx.y, smem);
+}
+
+// Several levels' translations in one launch (they are independent once
+// the upward pass is done): blocks [off[i], off[i + 1]) serve level i, each
+// with the arithmetic of k_translate.
+struct TranslateSet {
+  int32_t n;
+  int32_t off[TSET_MAX + 1];
+  DevLevel lv[TSET_MAX];
+  const void* S[TSET_MAX];
+  const void* T[TSET_MAX];
+  void* G[TSET_MAX];
+};
+
+template <typename TF>
+__global__ void __launch_bounds__(512) k_translate_set(TranslateSet ts, int Q, int R, int nsplit) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int v = blockIdx.x;
+  int i = 0;
+  while (i + 1 < ts.n && v >= ts.off[i + 1]) ++i;
+  const int loc = v - ts.off[i], nx = (int)xcd_grid(ts.lv[i].nb);
+  translate_body<TF>(ts.lv[i], (const cx<TF>*)ts.S[i], (const cx<TF>*)ts.T[i], (cx<TF>*)ts.G[i], Q, R, nsplit,
+                     loc % nx, loc / nx, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1382,6 +1414,38 @@ __global__ void __launch_bounds__(256) k_translate_batch(DevLevel Lv, const cx<T
 int translate_width(int Q) { return std::min(256, 64 * ((Q + 63) / 64)); }
 int translate_split(int Q) { return std::min(8, 512 / translate_width(Q)); }
 
+// Translations of n levels in one launch where every level takes the
+// single-column kernel (a batched pass, or more than TSET_MAX levels, uses
+// one launch per level); results equal the per-level launches bit for bit.
+template <typename TF>
+hipError_t launch_translate_levels(const DevLevel* lv, const void* const* S, const void* const* T, void* const* G,
+                                   int n, int Q, int R, hipStream_t st) {
+  const int width = translate_width(Q), ns = translate_split(Q);
+  bool single = n <= TSET_MAX;
+  for (int i = 0; i < n && single; ++i) single = !(R >= TB_MIN_COLS && lv[i].sib_ok);
+  if (!single) {
+    for (int i = 0; i < n; ++i) {
+      hipError_t e = launch_translate<TF>(lv[i], S[i], T[i], G[i], Q, R, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  if (n == 0) return hipSuccess;
+  TranslateSet ts{};
+  ts.n = n;
+  ts.off[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    ts.lv[i] = lv[i];
+    ts.S[i] = S[i];
+    ts.T[i] = T[i];
+    ts.G[i] = G[i];
+    ts.off[i + 1] = ts.off[i] + (int)xcd_grid(lv[i].nb) * R;
+  }
+  const size_t sm = 2 * (IL_MAX + 3) * sizeof(int32_t) + (size_t)(ns - 1) * width * 5 * 2 * sizeof(TF) + 16;
+  hipLaunchKernelGGL(k_translate_set<TF>, dim3(ts.off[n]), dim3(width * ns), sm, st, ts, Q, R, ns);
+  return hipGetLastError();
+}
+
 template <typename TF>
 hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, void* Gout, int Q, int R,
                             hipStream_t st) {
@@ -1437,6 +1501,8 @@ hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N,
                                           const void*, int, int, hipStream_t);                               \
   template hipError_t launch_shift_down<TF>(const DevLevel&, const void*, void*, const void*, const void*,   \
                                             int, int, hipStream_t);                                          \
+  template hipError_t launch_translate_levels<TF>(const DevLevel*, const void* const*, const void* const*,       \
+                                                 void* const*, int, int, int, hipStream_t);                    \
   template hipError_t launch_translate<TF>(const DevLevel&, const void*, const void*, void*, int, int,       \
                                            hipStream_t);                                                     \
   template hipError_t launch_permute_in<TF>(const void*, int, const int32_t*, int, int, int, void*,           \

@@ -44,6 +44,10 @@ hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const
 template <typename TF>
 hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, void* Gout, int Q, int R,
                             hipStream_t st);
+// Translations of n levels (arrays of n) in one launch where possible.
+template <typename TF>
+hipError_t launch_translate_levels(const DevLevel* lv, const void* const* S, const void* const* T, void* const* G,
+                                   int n, int Q, int R, hipStream_t st);
 template <typename TF, typename TN>
 hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxinc, int maxjoin,
                           const void* Gin, const void* M, const int32_t* anti, int Q, int Qh, const void* part,

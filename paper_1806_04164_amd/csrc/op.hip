@@ -862,6 +862,9 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
     // exist and joins it before the downward shift into that level.
     const bool perlev = L > 3 && op->sched_il == 3;
     const bool fork2 = L > 3 && (op->sched_il == 1 || op->sched_il == 2);
+    // il_fork 4: every level's translation in one launch after the upward
+    // pass (no stream fork)
+    const bool oneset = op->sched_il == 4;
     auto translate = [&](int l, hipStream_t s) {
       return stage(op, PIE_STAGE_TRANSLATE, s, [&] {
         return launch_translate<TF>(op->lv[l], op->dS[l], op->dTl[l], op->dG[l], Q, R, s);
@@ -904,9 +907,27 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
         if (ps) return ps;
       }
     }
-    for (int l = 3; l <= L; ++l)
-      if (perlev ? l == 3 : (l < L || !fork2))
-        if ((e = translate(l, st)) != hipSuccess) return hip_fail(e, "translate");
+    if (oneset) {
+      DevLevel lvs[24];
+      const void* Ss[24];
+      const void* Ts[24];
+      void* Gs[24];
+      const int n = L - 2;
+      for (int i = 0; i < n; ++i) {
+        lvs[i] = op->lv[3 + i];
+        Ss[i] = op->dS[3 + i];
+        Ts[i] = op->dTl[3 + i];
+        Gs[i] = op->dG[3 + i];
+      }
+      if ((e = stage(op, PIE_STAGE_TRANSLATE, st, [&] {
+             return launch_translate_levels<TF>(lvs, Ss, Ts, Gs, n, Q, R, st);
+           })) != hipSuccess)
+        return hip_fail(e, "translate");
+    } else {
+      for (int l = 3; l <= L; ++l)
+        if (perlev ? l == 3 : (l < L || !fork2))
+          if ((e = translate(l, st)) != hipSuccess) return hip_fail(e, "translate");
+    }
     for (int l = 4; l <= L; ++l) {
       if (l == L && fork2) HIPCHK(hipStreamWaitEvent(st, op->ev_il, 0), "join");
       if (perlev) HIPCHK(hipStreamWaitEvent(st, op->ev_g[l], 0), "join");
@@ -1244,7 +1265,7 @@ pie_status pie_schedule_set(pie_op* op, const pie_schedule* sch) {
     return PIE_ERR_ARG;
   }
   if (sch->near_fork < PIE_NEAR_SERIAL || sch->near_fork > PIE_NEAR_FORK_AFTER_AGGREGATE ||
-      (sch->il_fork < 0 || sch->il_fork > 3) ||
+      (sch->il_fork < 0 || sch->il_fork > 4) ||
       (sch->max_chunk != 1 && sch->max_chunk != 2 && sch->max_chunk != 4)) {
     pie::set_error("invalid schedule");
     return PIE_ERR_ARG;
@@ -1276,7 +1297,7 @@ pie_status pie_autotune(pie_op* op, const void* x, void* y, int64_t R, int32_t r
   s = PIE_OK;
   std::vector<pie_schedule> cand;
   for (int nf = PIE_NEAR_SERIAL; nf <= PIE_NEAR_FORK_AFTER_AGGREGATE; ++nf)
-    for (int il = 0; il <= 3; ++il)
+    for (int il = 0; il <= 4; ++il)
       for (int ch : {4, 2, 1})
         // register groups wider than R or than the operator's limit repeat a narrower one
         if (ch == 1 || (ch <= op->rc && ch <= R)) cand.push_back(pie_schedule{1, nf, il, ch});

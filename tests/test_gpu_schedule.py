@@ -45,7 +45,7 @@ def test_schedules_bitwise_equal(s4, near, far):
     ref = op.matvec(x).cpu().numpy()
     refa = op.matvec(x, adjoint=True).cpu().numpy()
     for nf, il, ch in itertools.product((PIE_NEAR_SERIAL, PIE_NEAR_FORK_START, PIE_NEAR_FORK_AFTER_AGGREGATE),
-                                        (0, 1, 2, 3), (1, 2, 4)):
+                                        (0, 1, 2, 3, 4), (1, 2, 4)):
         op.schedule = dict(near_fork=nf, il_fork=il, max_chunk=ch)
         assert op.schedule == dict(near_fork=nf, il_fork=il, max_chunk=ch)
         y = op.matvec(x).cpu().numpy()
@@ -55,9 +55,39 @@ def test_schedules_bitwise_equal(s4, near, far):
         assert np.array_equal(ya, refa)
 
 
+def test_one_launch_translations_five_levels():
+    """With five levels, il_fork 4 runs the translations of levels 3..5 in
+    one launch: eager MVMs and graph replays equal the serial schedule bit
+    for bit (mixed and FP32 far field, one and three columns, adjoint too)."""
+    V, T = synth.icosphere(5)
+    mesh = pie.Mesh(V, T)
+    tree = pie.Tree(mesh, 5)
+    f = 1e-3 * synth.C0 / synth.DIAMETER
+    for far, R in ((PIE_FP64, 1), (PIE_FP64, 3), (PIE_FP32, 1)):
+        op = pie.Operator(mesh, tree, f, near_prec=PIE_FP32, far_prec=far, max_rhs=R)
+        x = _x(op, R, 21)
+        op.schedule = dict(near_fork=PIE_NEAR_SERIAL, il_fork=0, max_chunk=1)
+        ref = op.matvec(x).cpu().numpy()
+        refa = op.matvec(x, adjoint=True).cpu().numpy()
+        for nf in (PIE_NEAR_SERIAL, PIE_NEAR_FORK_START, PIE_NEAR_FORK_AFTER_AGGREGATE):
+            op.schedule = dict(near_fork=nf, il_fork=4, max_chunk=1)
+            assert np.array_equal(op.matvec(x).cpu().numpy(), ref)
+            assert np.array_equal(op.matvec(x, adjoint=True).cpu().numpy(), refa)
+        y = torch.empty_like(x)
+        g = op.graph(x, y)
+        for rep in range(3):
+            y.zero_()
+            g.launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(y.cpu().numpy(), ref), (far, R, rep)
+            op.matvec(_x(op, R, 22))
+            torch.cuda.synchronize()
+        print("il_fork 4, five levels", far, R, flush=True)
+
+
 def test_schedule_validation(s4):
     op = _op(s4, max_rhs=1)
-    for bad in (dict(near_fork=3), dict(il_fork=4), dict(max_chunk=3)):
+    for bad in (dict(near_fork=3), dict(il_fork=5), dict(max_chunk=3)):
         with pytest.raises(PieError):
             op.schedule = bad
 
@@ -91,7 +121,8 @@ def test_graph_replays_match_eager(s4, adjoint):
         torch.cuda.synchronize()
     # a graph keeps the schedule it was captured with
     for sch in (dict(near_fork=PIE_NEAR_SERIAL, il_fork=0, max_chunk=1),
-                dict(near_fork=PIE_NEAR_FORK_START, il_fork=3, max_chunk=1)):
+                dict(near_fork=PIE_NEAR_FORK_START, il_fork=3, max_chunk=1),
+                dict(near_fork=PIE_NEAR_FORK_AFTER_AGGREGATE, il_fork=4, max_chunk=1)):
         op.schedule = sch
         g2 = op.graph(x, y, adjoint=adjoint)
         for rep in range(2):

@@ -166,8 +166,8 @@ def main():
                     help="after the run, copy MIB MiB device-to-device 5 times (hardware-counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is a "
-              f"design, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this implementation has no "
+              f"multi-GPU path (sharding is described in the design notes, not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -243,7 +243,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name if R == w.nrhs else f"{w.name} with {R} RHS", "unknowns": N, "rhs": R,
                    "levels": w.levels,
-                   "d_over_lambda": w.d_over_lambda, "subdivisions": w.subdiv,
+                   "shape": w.shape, "d_over_lambda": w.d_over_lambda, "subdivisions": w.subdiv,
                    "mode": head, "launch": res[head]["launch"], "schedule": res[head]["schedule"],
                    "gate_passed": gate[head]},
         "roofline": roof,

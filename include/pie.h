@@ -4,10 +4,12 @@
  * after Gur & Ergul, "Solutions of New Potential Integral Equations Using
  * MLFMA Based on the Approximate Stable Diagonalization" (arXiv:1806.04164).
  *
- * Problem (Section 2, Eqs. (1)-(2)): a closed triangulated surface S in free
- * space at angular frequency w, exp(-i w t) convention; unknowns are the
- * current J expanded in RWG functions (one per interior edge, E of them) and
- * n.A expanded in pulse functions (one per triangle, T of them), N = E + T.
+ * Problem (Section 2, Eqs. (1)-(2)): a triangulated surface S in free space,
+ * closed or open (Section 4 solves both a sphere and a flat patch), at
+ * angular frequency w, exp(-i w t) convention; unknowns are the current J
+ * expanded in RWG functions (one per interior edge, E of them; boundary
+ * edges of an open surface carry none) and n.A expanded in pulse functions
+ * (one per triangle, T of them), N = E + T.
  * Galerkin testing gives Z [a; b] = [b^J; b^A] with
  *   Z^JJ = mu0 <f_m, int f_n g>, Z^JA = <div f_m, int P_p g>,
  *   Z^AJ = <P_q, int div' f_n g>, Z^AA = w^2 eps0 <P_q, int P_p g>,

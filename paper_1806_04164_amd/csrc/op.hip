@@ -1157,10 +1157,6 @@ pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq
     pie::set_error("tau <= 20, Q <= 1024 and an even n_phi are required");
     return PIE_ERR_ARG;
   }
-  if (m->m.nboundary > 0) {
-    pie::set_error("open surfaces are not supported by this operator");
-    return PIE_ERR_UNSUPPORTED;
-  }
   const double d3 = t->t.side / 4.0;
   if (op->k * d3 > 1.0) {
     pie::set_error("level-3 boxes exceed 1/(2 pi) wavelengths: outside the low-frequency regime");

@@ -138,6 +138,73 @@ def icosphere(subdiv: int, radius: float = DIAMETER / 2, jitter: float = 0.0,
 
 
 # ----------------------------------------------------------------------------
+# Open surfaces (flat plates in the plane z = 0, normal +z)
+# ----------------------------------------------------------------------------
+def patch(n: int, edge: float = DIAMETER, cross: bool = False):
+    """Square plate [-edge/2, edge/2]^2 in z = 0 on an n x n grid of squares,
+    counter-clockwise seen from +z.  Each square is split into two triangles
+    along a diagonal whose direction alternates with (i + j) mod 2
+    (2 n^2 triangles; n = 75 gives the 11 250 triangles of the paper's patch),
+    or, with ``cross``, into four triangles around its centre (4 n^2
+    triangles, symmetric under x -> -x, y -> -y and x <-> y).
+    Returns (V float64 [nv,3], T int32 [nt,3])."""
+    g = (np.arange(n + 1) / n - 0.5) * edge
+    X, Y = np.meshgrid(g, g, indexing="ij")          # vertex (i, j) = i * (n + 1) + j
+    V = [np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], 1)]
+    vid = lambda i, j: i * (n + 1) + j
+    T = []
+    nc = (n + 1) ** 2
+    for i in range(n):
+        for j in range(n):
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)  # ccw corners
+            if cross:
+                m = nc + i * n + j
+                T += [(a, b, m), (b, c, m), (c, d, m), (d, a, m)]
+            elif (i + j) % 2 == 0:
+                T += [(a, b, c), (a, c, d)]
+            else:
+                T += [(a, b, d), (b, c, d)]
+    if cross:
+        cx = 0.5 * (g[:-1] + g[1:])
+        CX, CY = np.meshgrid(cx, cx, indexing="ij")
+        V.append(np.stack([CX.ravel(), CY.ravel(), np.zeros(CX.size)], 1))
+    return np.ascontiguousarray(np.concatenate(V)), np.ascontiguousarray(np.array(T, dtype=np.int32))
+
+
+def disk(rings: int, radius: float = DIAMETER / 2):
+    """Circular plate of the given radius in z = 0, counter-clockwise seen
+    from +z: a centre vertex and rings k = 1..rings of 6k vertices at radius
+    radius * k / rings (angles 2 pi m / (6k)); neighbouring rings are joined
+    by one strip of triangles, advancing on whichever ring's next vertex has
+    the smaller angle.  6 rings^2 triangles.  Returns (V, T)."""
+    V = [np.zeros((1, 3))]
+    start = [0]
+    for k in range(1, rings + 1):
+        th = 2.0 * np.pi * np.arange(6 * k) / (6 * k)
+        r = radius * k / rings
+        start.append(sum(len(v) for v in V))
+        V.append(np.stack([r * np.cos(th), r * np.sin(th), np.zeros(6 * k)], 1))
+    T = []
+    for m in range(6):                                  # centre fan
+        T.append((0, 1 + m, 1 + (m + 1) % 6))
+    for k in range(2, rings + 1):
+        n0, n1, s0, s1 = 6 * (k - 1), 6 * k, start[k - 1], start[k]
+        i0 = i1 = 0
+        while i0 < n0 or i1 < n1:
+            # angles of the next vertices (the ring closes at 1.0 = 2 pi)
+            t0 = (i0 + 1) / n0 if i0 < n0 else 2.0
+            t1 = (i1 + 1) / n1 if i1 < n1 else 2.0
+            a0, a1 = s0 + i0 % n0, s1 + i1 % n1
+            if t1 <= t0:
+                T.append((a0, a1, s1 + (i1 + 1) % n1))
+                i1 += 1
+            else:
+                T.append((a0, a1, s0 + (i0 + 1) % n0))
+                i0 += 1
+    return np.ascontiguousarray(np.concatenate(V)), np.ascontiguousarray(np.array(T, dtype=np.int32))
+
+
+# ----------------------------------------------------------------------------
 # Plane waves and coefficient vectors
 # ----------------------------------------------------------------------------
 def plane_waves(R: int, seed: int):
@@ -184,19 +251,22 @@ def sphere_directions(n: int, seed: int) -> np.ndarray:
 @dataclasses.dataclass(frozen=True)
 class Workload:
     name: str
-    subdiv: int
-    d_over_lambda: float
+    subdiv: int                  # sphere: subdivisions; patch: squares per edge
+    d_over_lambda: float         # sphere diameter or patch edge over the wavelength
     levels: int
     nrhs: int
     jitter: float = 0.0
     seed: int = 0
     rhs_seed: int | None = None  # None: the single axial wave
+    shape: str = "sphere"        # "sphere" or "patch"
 
     @property
     def freq(self) -> float:
         return self.d_over_lambda * C0 / DIAMETER
 
     def mesh(self):
+        if self.shape == "patch":
+            return patch(self.subdiv, DIAMETER)
         return icosphere(self.subdiv, DIAMETER / 2, self.jitter, self.seed)
 
     def waves(self):
@@ -217,6 +287,11 @@ WORKLOADS = {
     # sphere D = 1e-4 lambda, 20480 triangles, 16 plane waves, 5 levels
     "sphere_s5_1e-4lam_r16": Workload("sphere_s5_1e-4lam_r16", 5, 1e-4, 5, 16,
                                       rhs_seed=4),
+    # the paper's patch: 0.6 m edge, 75 x 75 squares (11 250 triangles,
+    # 16 725 RWG), axial wave, at 1 MHz (edge lambda/500) and 100 MHz
+    # (lambda/5); 5 levels (finest boxes of about 4.7 mesh edges)
+    "patch_75_1MHz": Workload("patch_75_1MHz", 75, 0.6 / (C0 / 1e6), 5, 1, shape="patch"),
+    "patch_75_100MHz": Workload("patch_75_100MHz", 75, 0.6 / (C0 / 1e8), 5, 1, shape="patch"),
 }
 
 

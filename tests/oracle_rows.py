@@ -17,6 +17,8 @@ def _mesh(spec):
         return synth.WORKLOADS[arg].mesh()
     if kind == "uneven":
         return synth.uneven_batch()[arg].mesh()
+    if kind == "patch":
+        return synth.patch(arg)
     raise ValueError(kind)
 
 

@@ -1,0 +1,165 @@
+"""Open surfaces on the GPU: the paper's metallic patch (Section 4, 0.6 m
+edge, axial plane wave polarised along x, at 1 MHz and 100 MHz, i.e. edge
+lambda/500 and lambda/5).  Boundary edges carry no RWG function; the pulse
+(charge) unknowns are on every triangle.
+
+* 16 x 16 patch (512 triangles, 736 RWG), 3 and 4 levels: the MVM against
+  the dense FP64 oracle per sub-operator, FP64 and mixed (FP32 near field)
+  operators, <= 1e-3 (the diagonalisation's truncation error); the GMRES
+  solution's far field against the dense LU solution (<= 1e-3) and the
+  3-level against the 4-level far field.
+* the paper's patch (75 x 75 squares, 11 250 triangles, 16 725 RWG):
+  sampled rows of the dense oracle against the 5- and 6-level mixed MVM
+  (graph replay) <= 1e-3, and the paper's level-consistency experiment: far-zone
+  field on the z-x plane from 5- and 6-level solves (mixed operator, FP64
+  residual refinement) agreeing to a small fraction of a dB.  With 3 or 4
+  levels a finest box would hold 440 to 1750 unknowns, above the kernels'
+  128; with 7 the boxes shrink to about one mesh edge, where the one-box
+  buffer no longer keeps the expansion error near 1e-3 (the oracle's own
+  MLFMA gives 4e-3 there), so the sweep covers 5 and 6 levels.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import mom
+from paper_1806_04164_amd import pie
+from paper_1806_04164_amd._lib import PIE_FP32, PIE_FP64
+from tests.oracle_rows import sampled_rows
+
+pytestmark = pytest.mark.gpu
+
+FREQS = (1e6, 1e8)
+# GMRES tolerances: at 1 MHz (edge lambda/500) the charge mode's small
+# eigenvalue meets the rounding floor of the FP64 MVM (linear to about 1e-8
+# at tau = 7, x = 0.05, amplified by the sampled translation) and GMRES
+# stalls near 2e-5, so the low-frequency solves stop at 1e-4.  On the
+# paper's patch at 100 MHz the 6-level refinement levels off near 3e-5 (its
+# inner GMRES no longer reaches 1e-3 within 6000 iterations; 5 levels reach
+# 2e-6 in 1800), so the level sweep stops at 1e-4 at both frequencies.
+TOL = {1e6: 1e-4, 1e8: 1e-7}
+TOL_SWEEP = {1e6: 1e-4, 1e8: 1e-4}
+_TH = np.linspace(0.0, np.pi, 181)
+ZX = np.stack([np.sin(_TH), 0 * _TH, np.cos(_TH)], 1)     # bistatic angle 0..180 deg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module", params=FREQS, ids=("1MHz", "100MHz"))
+def p16(request):
+    f = request.param
+    V, T = synth.patch(16)
+    prob = mom.Problem(V, T, f)
+    m = pie.Mesh(V, T)
+    return dict(f=f, prob=prob, Z=prob.dense(), mesh=m, E=prob.mesh.nE,
+                trees={L: pie.Tree(m, L) for L in (3, 4)})
+
+
+def _op(c, L, near=PIE_FP64, far=PIE_FP64):
+    return pie.Operator(c["mesh"], c["trees"][L], c["f"], near_prec=near, far_prec=far)
+
+
+@pytest.mark.parametrize("L", (3, 4))
+@pytest.mark.parametrize("near", (PIE_FP64, PIE_FP32), ids=("fp64", "mixed"))
+def test_patch_matvec_against_dense(p16, L, near):
+    op = _op(p16, L, near=near)
+    E, Z = p16["E"], p16["Z"]
+    x = synth.complex_gaussian(op.N, 1, 7)[:, 0]
+    errs = {}
+    for name, sl in (("J", slice(0, E)), ("A", slice(E, None))):
+        xm = np.zeros_like(x)
+        xm[sl] = x[sl]
+        y = host(op.matvec(dev(xm[:, None])))[:, 0]
+        yr = Z @ xm
+        for rn, rs in (("J", slice(0, E)), ("A", slice(E, None))):
+            errs[rn + name] = np.linalg.norm(y[rs] - yr[rs]) / np.linalg.norm(yr[rs])
+    print("patch 16", p16["f"], "L", L, "near", near, errs, flush=True)
+    assert max(errs.values()) <= 1e-3
+
+
+def test_patch_solve_against_lu(p16):
+    prob = p16["prob"]
+    xd = np.linalg.solve(p16["Z"], prob.rhs(*synth.axial_wave())[:, 0])
+    Fd = prob.farfield(xd, ZX)[0]
+    F = {}
+    for L in (3, 4):
+        op = _op(p16, L)
+        b = op.rhs_planewave(*synth.axial_wave())
+        x, info = op.solve(b, tol=TOL[p16["f"]], restart=200, maxit=3000)
+        print("patch 16", p16["f"], "L", L, info, flush=True)
+        assert info["converged"]
+        F[L] = host(op.farfield(x, ZX))[0]
+        ef = np.linalg.norm(F[L] - Fd) / np.linalg.norm(Fd)
+        print("  far field vs dense LU", ef, flush=True)
+        assert ef < 1e-3
+    assert np.linalg.norm(F[3] - F[4]) < 2e-3 * np.linalg.norm(F[3])
+
+
+def _intensity_db(F):
+    return 10.0 * np.log10(np.sum(np.abs(F) ** 2, axis=-1))
+
+
+@pytest.fixture(scope="module")
+def p75():
+    V, T = synth.patch(75)
+    m = pie.Mesh(V, T)
+    return dict(V=V, T=T, mesh=m, E=m.sizes()[0], trees={L: pie.Tree(m, L) for L in (5, 6)})
+
+
+@pytest.mark.parametrize("L", (5, 6))
+@pytest.mark.parametrize("f", FREQS, ids=("1MHz", "100MHz"))
+def test_paper_patch_sampled_rows(p75, f, L):
+    op = pie.Operator(p75["mesh"], p75["trees"][L], f, near_prec=PIE_FP32, far_prec=PIE_FP64)
+    N, E = op.N, p75["E"]
+    rng = np.random.default_rng(11)
+    rows = np.sort(np.concatenate([rng.choice(E, 6, replace=False), E + rng.choice(N - E, 6, replace=False)]))
+    ref = sampled_rows([(("patch", 75), f, rows, 81, 1)])[0]
+    x = synth.complex_gaussian(N, 1, 81)
+    errs = {}
+    for name, sl in (("J", slice(0, E)), ("A", slice(E, None))):
+        xm = np.zeros_like(x)
+        xm[sl] = x[sl]
+        xd = dev(xm)
+        y = torch.empty_like(xd)
+        op.graph(xd, y).launch()
+        y = host(y)[rows]
+        for rn, rs in (("J", rows < E), ("A", rows >= E)):
+            errs[rn + name] = np.linalg.norm(y[rs] - ref[name][rs]) / np.linalg.norm(ref[name][rs])
+    print("patch 75", f, "L", L, errs, flush=True)
+    assert max(errs.values()) <= 1e-3
+
+
+@pytest.mark.parametrize("f", FREQS, ids=("1MHz", "100MHz"))
+def test_paper_patch_level_consistency(p75, f):
+    dB, FF = {}, {}
+    for L in (5, 6):
+        tr = p75["trees"][L]
+        fast = pie.Operator(p75["mesh"], tr, f, near_prec=PIE_FP32, far_prec=PIE_FP64)
+        ref = pie.Operator(p75["mesh"], tr, f, near_prec=PIE_FP64, far_prec=PIE_FP64)
+        b = ref.rhs_planewave(*synth.axial_wave())
+        tol = TOL_SWEEP[f]
+        x, info = fast.solve(b, res_op=ref, tol=tol, inner_tol=1e-3, refine=40, restart=200, maxit=6000)
+        print("patch 75", f, "L", L, info, flush=True)
+        assert info["converged"] and info["rel_residual"] <= tol
+        F = host(ref.farfield(x, ZX))[0]
+        FF[L] = F
+        dB[L] = _intensity_db(F)
+        # a flat scatterer radiates symmetrically about its plane
+        assert np.max(np.abs(dB[L] - dB[L][::-1])) < 1e-6
+    # the E-plane pattern of the x-directed current has a null at grazing
+    # incidence (90 deg); dB are compared within 20 dB of the peak
+    rel = np.linalg.norm(FF[5] - FF[6]) / np.linalg.norm(FF[6])
+    keep = dB[6] >= dB[6].max() - 20.0
+    d = np.max(np.abs(dB[5] - dB[6])[keep])
+    print("patch 75", f, "far-zone intensity (dB, 0..180 deg every 30):", np.round(dB[6][::30], 4),
+          "5 vs 6 levels: relative far-field difference", rel, "max |dB difference| within 20 dB of the peak",
+          d, flush=True)
+    assert rel < 2e-3 and d < 0.02

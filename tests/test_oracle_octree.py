@@ -9,9 +9,15 @@ import synth
 from oracle import mesh, octree
 
 
-@pytest.mark.parametrize("s,L", [(2, 3), (3, 4), (4, 5)])
+@pytest.mark.parametrize("s,L", [(2, 3), (3, 4), (4, 5), ("patch", 5), ("disk", 4)])
 def test_partition_of_pairs(s, L):
-    V, T = synth.icosphere(s, jitter=0.05, seed=3)
+    # spheres, and flat open plates lying on box faces (z = 0)
+    if s == "patch":
+        V, T = synth.patch(12)
+    elif s == "disk":
+        V, T = synth.disk(8)
+    else:
+        V, T = synth.icosphere(s, jitter=0.05, seed=3)
     m = mesh.build(V, T)
     tr = octree.build(m, L)
     nb = tr.levels[L].coords.shape[0]

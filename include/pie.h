@@ -325,6 +325,29 @@ pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void* x,
                      int64_t R, const pie_solve_opts* opts,
                      pie_solve_info* info, void* stream);
 
+/* ------------------------------------------------------- near-zone charge --
+ * Section 2 (the paragraph after Eq. (2)): the surface charge density for
+ * near-zone fields, rho = i w eps0 n.A - eps0 n.grad(Phi), where
+ * sigma = n.grad(Phi) solves Eq. (3),  int_S sigma(r') g(r,r') dr' = Phi^inc(r)
+ * on S.  sigma is expanded in the pulse functions and Eq. (3) is tested with
+ * them: S sigma = phi, S_qp = <P_q, int P_p g> (the pulse-pulse block of Z
+ * divided by w^2 eps0, applied with the same MLFMA), phi_q = <P_q, Phi^inc>
+ * for R plane waves (khat, pol, amp and gauge as in pie_rhs_planewave; use the
+ * gauge of the PIE right-hand side).  GMRES on the equilibrated pulse block
+ * with opts->tol, restart, maxit, refine, inner_tol (opts NULL: defaults;
+ * adjoint must be 0).
+ * x:     device complex128 [N][R], the PIE solution (its pulse rows are n.A);
+ *        may be NULL when rho is NULL.
+ * sigma: device complex128 [T][R] out, n.grad(Phi) per triangle (triangle order).
+ * rho:   device complex128 [T][R] out (C/m^2 for E0 = 1 V/m), or NULL.
+ * Allocates a 2 N R complex128 workspace.  Returns PIE_WARN_NOT_CONVERGED if
+ * GMRES stops above tol (the outputs hold the last iterate). */
+pie_status pie_charge(pie_op* op, int64_t R, const double* khat,
+                      const double* pol, const double* amp, int32_t gauge,
+                      const void* x, void* sigma, void* rho,
+                      const pie_solve_opts* opts, pie_solve_info* info,
+                      void* stream);
+
 /* ---------------------------------------------------------- far field --
  * F(rhat) = lim r e^{-ikr} E^s = (i w mu0 / 4 pi)(I - rhat rhat).
  *           int J(r') exp(-i k rhat.r') dr',  J = sum a_n f_n.

@@ -260,6 +260,31 @@ class Problem:
             b[m.nE:, r] = -1j * self.omega * EPS0 * np.sum(self.W * Phi, axis=1)
         return b
 
+    def charge(self, x, khat, pol, amp, gauge=0):
+        """Near-zone charge density per triangle (Section 2, the paragraph
+        after Eq. (2)).  sigma = n.grad(Phi) solves Eq. (3),
+            int_S sigma(r') g(r, r') dr' = Phi^inc(r)   (r on S),
+        with sigma expanded in the pulse functions and tested with them:
+            sum_p sigma_p <P_q, int P_p g> = <P_q, Phi^inc>
+        (the pulse-pulse matrix is Z^AA / (w^2 eps0)); then
+            rho = i w eps0 (n.A) - eps0 sigma,
+        with n.A the pulse part of the PIE solution x [N,R].
+        Returns (sigma [T,R], rho [T,R])."""
+        m = self.mesh
+        x = np.asarray(x).reshape(self.N, -1)
+        khat = np.atleast_2d(khat)
+        pol = np.atleast_2d(pol)
+        amp = np.atleast_1d(amp)
+        idx = np.arange(m.nE, self.N)
+        S = self.zblock(idx, idx) / (self.omega ** 2 * EPS0)
+        phi = np.zeros((m.nT, khat.shape[0]), dtype=np.complex128)
+        for r in range(khat.shape[0]):
+            _, Phi = self.incident_potentials(self.P, khat[r], pol[r], amp[r], 0 if gauge == 0 else 1)
+            phi[:, r] = np.sum(self.W * Phi, axis=1)
+        sigma = np.linalg.solve(S, phi)
+        rho = 1j * self.omega * EPS0 * x[m.nE:] - EPS0 * sigma
+        return sigma, rho
+
     def current_radiation(self, x, dirs):
         """int J(r') exp(-i k rhat.r') dr' for J = sum a_n f_n;
         x [N,R] or [N]; returns [R,nd,3]."""

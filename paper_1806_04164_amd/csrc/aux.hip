@@ -307,4 +307,35 @@ hipError_t launch_sub(const void* a, const void* b, int N, int R, void* out, hip
   return hipGetLastError();
 }
 
+// Right-hand side of the charge equation from a plane-wave one: RWG rows
+// cleared, pulse rows times c.
+__global__ void k_pulse_rhs(cx<double>* __restrict__ b, int64_t nj, int64_t n, cx<double> c) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  b[e] = e < nj ? mk(0.0, 0.0) : c * b[e];
+}
+hipError_t launch_pulse_rhs(void* b, int E, int N, int R, double cre, double cim, hipStream_t st) {
+  const int64_t n = (int64_t)N * R;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pulse_rhs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (cx<double>*)b,
+                     (int64_t)E * R, n, mk(cre, cim));
+  return hipGetLastError();
+}
+
+// rho = i w eps0 (n.A) - eps0 sigma, per triangle and column.
+__global__ void k_charge_rho(const cx<double>* __restrict__ na, const cx<double>* __restrict__ sigma, int64_t n,
+                             double weps0, double eps0, cx<double>* __restrict__ rho) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const cx<double> a = na[e], s = sigma[e];
+  rho[e] = mk(-weps0 * a.im - eps0 * s.re, weps0 * a.re - eps0 * s.im);
+}
+hipError_t launch_charge_rho(const cx<double>* na, const cx<double>* sigma, int64_t n, double weps0, double eps0,
+                             void* rho, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_charge_rho, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, na, sigma, n, weps0, eps0,
+                     (cx<double>*)rho);
+  return hipGetLastError();
+}
+
 }  // namespace pie

@@ -76,5 +76,10 @@ hipError_t launch_norms(const void* w, int N, int R, double* out, hipStream_t st
 hipError_t launch_colscale(void* w, const double* s, int N, int R, hipStream_t st);
 hipError_t launch_axpy_cols(void* x, const void* y, const void* a, int N, int R, hipStream_t st);
 hipError_t launch_sub(const void* a, const void* b, int N, int R, void* out, hipStream_t st);
+// Charge equation (pulse-pulse block): b <- RWG rows cleared, pulse rows
+// times (cre + i cim); rho = i weps0 na - eps0 sigma, n entries.
+hipError_t launch_pulse_rhs(void* b, int E, int N, int R, double cre, double cim, hipStream_t st);
+hipError_t launch_charge_rho(const cx<double>* na, const cx<double>* sigma, int64_t n, double weps0, double eps0,
+                             void* rho, hipStream_t st);
 
 }  // namespace pie

@@ -1553,8 +1553,23 @@ namespace {
 // GMRES(m) with CGS2 on the equilibrated operator D Z D for all R columns in
 // lock step; each column keeps its own Hessenberg matrix and rotations and is
 // frozen once its residual estimate meets tol.  xhat (device) is updated.
+// The operator of a solve: mvm flags (3 = near + far, 4 = adjoint) plus
+// SOLVE_PULSE_BLOCK, which applies the pulse-pulse block alone, embedded as
+// diag(0, Z^AA): the RWG rows of the input are cleared before the product
+// and those of the output after it, so a right-hand side without RWG rows
+// keeps every Krylov vector in the pulse rows.
+constexpr int SOLVE_PULSE_BLOCK = 8;
+pie_status solve_mvm(pie_op* op, cx<double>* x, cx<double>* y, int64_t R, int flags, hipStream_t st) {
+  const size_t nj = (size_t)op->ne * R * sizeof(cx<double>);
+  if (flags & SOLVE_PULSE_BLOCK) HIPCHK(hipMemsetAsync(x, 0, nj, st), "clear RWG rows");
+  pie_status s = mvm(op, x, y, R, flags & 7, st);
+  if (s) return s;
+  if (flags & SOLVE_PULSE_BLOCK) HIPCHK(hipMemsetAsync(y, 0, nj, st), "clear RWG rows");
+  return PIE_OK;
+}
+
 pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xhat, int R, const pie_solve_opts& o,
-                              double tol, int adjoint, int* iters, hipStream_t st, cx<double>* work) {
+                              double tol, int mflags, int* iters, hipStream_t st, cx<double>* work) {
   const int N = op->N, m = std::max(1, o.restart);
   const size_t NR = (size_t)N * R;
   cx<double>* V = work;                    // (m+1) blocks
@@ -1579,7 +1594,7 @@ pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xh
   while (total < o.maxit) {
     // r = rhat - A xhat  (A = D Z D)
     if ((e = launch_scale_rows(xhat, op->dDiagScale, N, R, tmp, st)) != hipSuccess) return hip_fail(e, "scale");
-    if ((s = mvm(op, tmp, w, R, 3 | (adjoint ? 4 : 0), st))) return s;
+    if ((s = solve_mvm(op, tmp, w, R, mflags, st))) return s;
     if ((e = launch_scale_rows(w, op->dDiagScale, N, R, w, st)) != hipSuccess) return hip_fail(e, "scale");
     if ((e = launch_sub(rhat, w, N, R, V, st)) != hipSuccess) return hip_fail(e, "sub");
     if ((e = launch_norms(V, N, R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
@@ -1605,7 +1620,7 @@ pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xh
       ++total;
       cx<double>* vj = V + (size_t)j * NR;
       if ((e = launch_scale_rows(vj, op->dDiagScale, N, R, tmp, st)) != hipSuccess) return hip_fail(e, "scale");
-      if ((s = mvm(op, tmp, w, R, 3 | (adjoint ? 4 : 0), st))) return s;
+      if ((s = solve_mvm(op, tmp, w, R, mflags, st))) return s;
       if ((e = launch_scale_rows(w, op->dDiagScale, N, R, w, st)) != hipSuccess) return hip_fail(e, "scale");
       // classical Gram-Schmidt, twice
       if ((s = dots(j + 1, h))) return s;
@@ -1680,8 +1695,10 @@ pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xh
 
 }  // namespace
 
-extern "C" pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void* x, int64_t R,
-                                const pie_solve_opts* opts, pie_solve_info* info, void* stream) {
+// GMRES with outer refinement for Z x = b, or (block = SOLVE_PULSE_BLOCK)
+// for the pulse-pulse block alone.
+static pie_status solve_core(pie_op* op, pie_op* res_op, const void* b, void* x, int64_t R,
+                             const pie_solve_opts* opts, pie_solve_info* info, void* stream, int block) {
   pie_status s = check_op_call(op, b, x, R);
   if (s) return s;
   pie_solve_opts o;
@@ -1725,7 +1742,7 @@ extern "C" pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void*
   double relmax = 0.0;
   for (int k = 0; k < o.refine; ++k) {
     // residual with the residual operator
-    if ((s = mvm(rop, X, zx, R, 3 | (o.adjoint ? 4 : 0), st))) return s;
+    if ((s = solve_mvm(rop, X, zx, R, 3 | (o.adjoint ? 4 : 0) | block, st))) return s;
     if ((e = pie::launch_sub(b, zx, N, (int)R, rr, st)) != hipSuccess) return hip_fail(e, "sub");
     if ((e = pie::launch_norms(rr, N, (int)R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
     HIPCHK(hipMemcpyAsync(rn.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
@@ -1737,7 +1754,8 @@ extern "C" pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void*
     if ((e = pie::launch_scale_rows(rr, op->dDiagScale, N, (int)R, rhat, st)) != hipSuccess) return hip_fail(e, "scale");
     HIPCHK(hipMemsetAsync(xh, 0, NR * 16, st), "zero");
     int it = 0;
-    if ((s = gmres_equilibrated(op, rhat, xh, (int)R, o, inner, o.adjoint, &it, st, work))) return s;
+    if ((s = gmres_equilibrated(op, rhat, xh, (int)R, o, inner, 3 | (o.adjoint ? 4 : 0) | block, &it, st, work)))
+      return s;
     iters += it;
     if ((e = pie::launch_scale_rows(xh, op->dDiagScale, N, (int)R, xh, st)) != hipSuccess) return hip_fail(e, "scale");
     std::vector<cx<double>> one(R, cx<double>{1.0, 0.0});
@@ -1745,7 +1763,7 @@ extern "C" pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void*
     if ((e = pie::launch_axpy_cols(X, xh, dn, N, (int)R, st)) != hipSuccess) return hip_fail(e, "axpy");
     HIPCHK(hipStreamSynchronize(st), "solve");
     if (k == o.refine - 1) {
-      if ((s = mvm(rop, X, zx, R, 3 | (o.adjoint ? 4 : 0), st))) return s;
+      if ((s = solve_mvm(rop, X, zx, R, 3 | (o.adjoint ? 4 : 0) | block, st))) return s;
       if ((e = pie::launch_sub(b, zx, N, (int)R, rr, st)) != hipSuccess) return hip_fail(e, "sub");
       if ((e = pie::launch_norms(rr, N, (int)R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
       HIPCHK(hipMemcpyAsync(rn.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
@@ -1760,4 +1778,57 @@ extern "C" pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void*
     info->rel_residual = relmax;
   }
   return relmax <= o.tol ? PIE_OK : PIE_WARN_NOT_CONVERGED;
+}
+
+extern "C" pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void* x, int64_t R,
+                                const pie_solve_opts* opts, pie_solve_info* info, void* stream) {
+  return solve_core(op, res_op, b, x, R, opts, info, stream, 0);
+}
+
+extern "C" pie_status pie_charge(pie_op* op, int64_t R, const double* khat, const double* pol, const double* amp,
+                                 int32_t gauge, const void* x, void* sigma, void* rho,
+                                 const pie_solve_opts* opts, pie_solve_info* info, void* stream) {
+  if (!op || !khat || !pol || !amp || !sigma || (rho && !x)) {
+    pie::set_error("null argument (rho needs the PIE solution x)");
+    return PIE_ERR_ARG;
+  }
+  if (R < 1 || R > op->max_rhs) {
+    pie::set_error("R must be in [1, max_rhs]");
+    return PIE_ERR_ARG;
+  }
+  if (opts && opts->adjoint) {
+    pie::set_error("the charge solve has no adjoint");
+    return PIE_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int N = op->N, E = op->ne, T = op->nt;
+  const size_t NR = (size_t)N * R;
+  cx<double>* buf = nullptr;
+  HIPCHK(hipMalloc(&buf, 2 * NR * sizeof(cx<double>)), "charge workspace");
+  std::unique_ptr<void, void (*)(void*)> guard(buf, [](void* p) { (void)hipFree(p); });
+  cx<double>* b = buf;
+  cx<double>* X = buf + NR;
+  // right-hand side of Eq. (3) tested with the pulses, scaled by w^2 eps0 to
+  // match the pulse-pulse block of Z: the plane-wave pulse rows are
+  // -i w eps0 <P_q, Phi^inc>, times i w
+  pie_status s = pie_rhs_planewave(op, R, khat, pol, amp, gauge, b, stream);
+  if (s) return s;
+  hipError_t e = pie::launch_pulse_rhs(b, E, N, (int)R, 0.0, op->omega, st);
+  if (e != hipSuccess) return hip_fail(e, "charge rhs");
+  pie_solve_opts o;
+  pie_solve_opts_default(&o);
+  if (opts) o = *opts;
+  o.use_x0 = 0;
+  s = solve_core(op, nullptr, b, X, R, &o, info, stream, SOLVE_PULSE_BLOCK);
+  if (s != PIE_OK && s != PIE_WARN_NOT_CONVERGED) return s;
+  // sigma = pulse rows of the block solution; rho = i w eps0 (n.A) - eps0 sigma
+  HIPCHK(hipMemcpyAsync(sigma, X + (size_t)E * R, (size_t)T * R * sizeof(cx<double>), hipMemcpyDeviceToDevice, st),
+         "sigma copy");
+  if (rho) {
+    e = pie::launch_charge_rho((const cx<double>*)x + (size_t)E * R, (const cx<double>*)sigma, (int64_t)T * R,
+                               op->omega * pie::kEps0, pie::kEps0, rho, st);
+    if (e != hipSuccess) return hip_fail(e, "rho");
+  }
+  HIPCHK(hipStreamSynchronize(st), "charge");
+  return s;
 }

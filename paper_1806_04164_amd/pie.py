@@ -289,6 +289,31 @@ class Operator:
         return x, {"iterations": info.iterations, "refinements": info.refinements,
                    "rel_residual": info.rel_residual, "converged": st == 0}
 
+    def charge(self, khat, pol, amp, x=None, gauge=0, tol=1e-6, restart=100, maxit=1000, refine=1,
+               inner_tol=0.0, stream=None):
+        """pie_charge: sigma = n.grad(Phi) [T,R] from Eq. (3) and, given the
+        PIE solution x [N,R], the charge density rho [T,R]."""
+        import torch
+        khat = np.ascontiguousarray(np.atleast_2d(khat), np.float64)
+        pol = np.ascontiguousarray(np.atleast_2d(pol), np.float64)
+        amp = np.ascontiguousarray(np.atleast_1d(amp), np.complex128)
+        R = khat.shape[0]
+        T = self.mesh.sizes()[1]
+        o = _lib.pie_solve_opts()
+        lib().pie_solve_opts_default(ctypes.byref(o))
+        o.tol, o.restart, o.maxit, o.refine, o.inner_tol = tol, restart, maxit, refine, inner_tol
+        sigma = torch.empty((T, R), dtype=torch.complex128, device="cuda")
+        rho = torch.empty((T, R), dtype=torch.complex128, device="cuda") if x is not None else None
+        info = _lib.pie_solve_info()
+        st = lib().pie_charge(self.h, R, _ptr(khat), _ptr(pol), _ptr(amp), gauge,
+                              _dev(x, self.N, R) if x is not None else None,
+                              ctypes.c_void_p(sigma.data_ptr()),
+                              ctypes.c_void_p(rho.data_ptr()) if rho is not None else None,
+                              ctypes.byref(o), ctypes.byref(info), _stream(stream))
+        check(st)
+        return sigma, rho, {"iterations": info.iterations, "refinements": info.refinements,
+                            "rel_residual": info.rel_residual, "converged": st == 0}
+
     def farfield(self, x, dirs, stream=None):
         import torch
         R = self._R(x)

@@ -111,3 +111,4 @@ def test_operator_argument_validation_without_gpu():
     # null handles on the MVM entry points
     assert L.pie_matvec(None, None, None, 1, 0, None) == _lib.PIE_ERR_ARG
     assert L.pie_solve(None, None, None, None, 1, None, None, None) == _lib.PIE_ERR_ARG
+    assert L.pie_charge(None, 1, None, None, None, 0, None, None, None, None, None, None) == _lib.PIE_ERR_ARG

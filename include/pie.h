@@ -306,7 +306,7 @@ pie_status pie_rhs_planewave(pie_op* op, int64_t R, const double* khat,
  * info (host, may be NULL) receives iterations and final relative residual
  * per RHS. Returns PIE_WARN_NOT_CONVERGED if any RHS missed tol. */
 typedef struct pie_solve_opts {
-  int32_t version;    /* must be 1                                    */
+  int32_t version;    /* 2 (1: the fields up to adjoint, precond = 0)  */
   int32_t restart;    /* Krylov dimension per cycle (default 100)     */
   int32_t maxit;      /* total inner iterations per RHS (default 1000) */
   int32_t refine;     /* outer refinement steps (default 1 = none)    */
@@ -314,6 +314,10 @@ typedef struct pie_solve_opts {
   double inner_tol;   /* inner tolerance per refinement (default tol) */
   int32_t use_x0;     /* 1: x holds the initial guess                 */
   int32_t adjoint;    /* 1: solve Z^H x = b                           */
+  int32_t precond;    /* 1: right block-diagonal preconditioner: the   */
+                      /* inverses of the finest boxes' FP64 self      */
+                      /* blocks (built on the first such solve, kept  */
+                      /* with the operator: 16 sum n_b^2 bytes)       */
 } pie_solve_opts;
 typedef struct pie_solve_info {
   int32_t iterations; /* total inner iterations (max over RHS)        */
@@ -324,6 +328,14 @@ void pie_solve_opts_default(pie_solve_opts* o);
 pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void* x,
                      int64_t R, const pie_solve_opts* opts,
                      pie_solve_info* info, void* stream);
+
+/* Block-diagonal preconditioner of the solve (precond = 1): y = M^-1 x with
+ * M = blockdiag(Z_bb) over the finest boxes b (FP64 self blocks, inverted on
+ * the host at the first use and kept with the operator), for callers with
+ * their own Krylov solver.  x, y: device complex128 [N][R], canonical order,
+ * not overlapping. */
+pie_status pie_precond_apply(pie_op* op, const void* x, void* y, int64_t R,
+                             void* stream);
 
 /* ------------------------------------------------------- near-zone charge --
  * Section 2 (the paragraph after Eq. (2)): the surface charge density for

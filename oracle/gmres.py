@@ -3,7 +3,11 @@ paper states neither restart, tolerance nor preconditioner).
 
 Arnoldi with modified Gram-Schmidt, Givens rotations on the Hessenberg
 matrix, stop when ||b - A x|| <= tol ||b||.  One right-hand side at a time.
-Pin: agreement with a direct LU solve (tests/test_oracle_gmres.py).
+Pins (tests/test_oracle_gmres.py): agreement with a direct LU solve, and
+the defining property of GMRES: after k steps without restart the residual
+is the least-squares minimum of ||b - A z|| over the Krylov space
+span{b, A b, ..., A^(k-1) b}, checked by brute force on a small complex
+matrix.
 """
 from __future__ import annotations
 
@@ -40,9 +44,12 @@ def gmres(matvec, b, x0=None, tol=1e-8, restart=100, maxit=1000):
             H[j + 1, j] = np.linalg.norm(w)
             if H[j + 1, j] != 0.0:
                 Vb[j + 1] = w / H[j + 1, j]
+            # rotation i is G = [[conj(c), conj(s)], [-s, c]], which maps
+            # (H[i, i], H[i + 1, i]) to (|.|, 0); the same G acts on the
+            # later columns and on g
             for i in range(j):
-                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
-                H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + np.conj(cs[i]) * H[i + 1, j]
+                t = np.conj(cs[i]) * H[i, j] + np.conj(sn[i]) * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
                 H[i, j] = t
             a, c = H[j, j], H[j + 1, j]
             den = np.sqrt(abs(a) ** 2 + abs(c) ** 2)
@@ -50,7 +57,7 @@ def gmres(matvec, b, x0=None, tol=1e-8, restart=100, maxit=1000):
             sn[j] = c / den if den else 0.0
             H[j, j] = den
             H[j + 1, j] = 0.0
-            g[j + 1] = -np.conj(sn[j]) * g[j]
+            g[j + 1] = -sn[j] * g[j]
             g[j] = np.conj(cs[j]) * g[j]
             it += 1
             j_used = j + 1

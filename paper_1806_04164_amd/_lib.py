@@ -42,7 +42,7 @@ EXPORTS = [
     "pie_mesh_edges", "pie_tree_build", "pie_tree_destroy", "pie_tree_query",
     "pie_options_default", "pie_operator_create", "pie_operator_destroy", "pie_operator_info",
     "pie_operator_level", "pie_matvec", "pie_matvec_near", "pie_matvec_far",
-    "pie_rhs_planewave", "pie_solve_opts_default", "pie_solve", "pie_charge", "pie_farfield",
+    "pie_rhs_planewave", "pie_solve_opts_default", "pie_solve", "pie_precond_apply", "pie_charge", "pie_farfield",
     "pie_profile_enable", "pie_profile_read", "pie_farfield_adjoint",
     "pie_schedule_get", "pie_schedule_set", "pie_autotune",
     "pie_graph_create", "pie_graph_launch", "pie_graph_destroy", "pie_graph_create_batch",
@@ -66,7 +66,7 @@ class pie_solve_opts(ctypes.Structure):
     _fields_ = [("version", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("refine", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("inner_tol", ctypes.c_double), ("use_x0", ctypes.c_int32),
-                ("adjoint", ctypes.c_int32)]
+                ("adjoint", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class pie_solve_info(ctypes.Structure):
@@ -108,6 +108,7 @@ def lib():
         "pie_solve_opts_default": (None, [ctypes.POINTER(pie_solve_opts)]),
         "pie_solve": (I32, [P, P, P, P, I64, ctypes.POINTER(pie_solve_opts),
                             ctypes.POINTER(pie_solve_info), P]),
+        "pie_precond_apply": (I32, [P, P, P, I64, P]),
         "pie_charge": (I32, [P, I64, P, P, P, I32, P, P, P, ctypes.POINTER(pie_solve_opts),
                              ctypes.POINTER(pie_solve_info), P]),
         "pie_farfield": (I32, [P, P, I64, P, I64, P, P]),

@@ -338,4 +338,49 @@ hipError_t launch_charge_rho(const cx<double>* na, const cx<double>* sigma, int6
   return hipGetLastError();
 }
 
+// Block-diagonal preconditioner: for every finest box b,
+//   y[perm[u]] = sum_{v in b} Minv_b[u][v] x[perm[v]] / d[perm[v]]
+// (R columns; Minv_b row-major nb x nb at off[b], box order; d NULL: 1).
+__global__ void __launch_bounds__(128) k_block_prec(const cx<double>* __restrict__ x, const double* __restrict__ d,
+                                                    const cx<double>* __restrict__ minv,
+                                                    const int64_t* __restrict__ off,
+                                                    const int32_t* __restrict__ box_ptr,
+                                                    const int32_t* __restrict__ perm, int R,
+                                                    cx<double>* __restrict__ y) {
+  const int b = blockIdx.x;
+  const int u0 = box_ptr[b], nb = box_ptr[b + 1] - u0;
+  const cx<double>* M = minv + off[b];
+  for (int e = threadIdx.x; e < nb * R; e += blockDim.x) {
+    const int i = e / R, r = e - i * R;
+    cx<double> acc = mk(0.0, 0.0);
+    for (int j = 0; j < nb; ++j) {
+      const int cv = perm[u0 + j];
+      cfma(acc, M[(size_t)i * nb + j], (d ? 1.0 / d[cv] : 1.0) * x[(size_t)cv * R + r]);
+    }
+    y[(size_t)perm[u0 + i] * R + r] = acc;
+  }
+}
+hipError_t launch_block_prec(const void* x, const double* d, const void* minv, const int64_t* off,
+                             const int32_t* box_ptr, const int32_t* perm, int nbox, int R, void* y, hipStream_t st) {
+  if (nbox <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_block_prec, dim3(nbox), dim3(128), 0, st, (const cx<double>*)x, d, (const cx<double>*)minv,
+                     off, box_ptr, perm, R, (cx<double>*)y);
+  return hipGetLastError();
+}
+
+// x += t / d (per row), n = N R entries.
+__global__ void k_add_scaled(cx<double>* __restrict__ x, const cx<double>* __restrict__ t,
+                             const double* __restrict__ d, int64_t n, int R) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  x[e] = x[e] + (1.0 / d[e / R]) * t[e];
+}
+hipError_t launch_add_scaled(void* x, const void* t, const double* d, int N, int R, hipStream_t st) {
+  const int64_t n = (int64_t)N * R;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_scaled, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (cx<double>*)x,
+                     (const cx<double>*)t, d, n, R);
+  return hipGetLastError();
+}
+
 }  // namespace pie

@@ -13,6 +13,9 @@ hipError_t launch_near_fill(const DevGeo& G, const DevBasis& B, const DevNear& N
                             double w2e, hipStream_t st);
 hipError_t launch_diag(const DevGeo& G, const DevBasis& B, double* diag_abs, double k, double w2e,
                        hipStream_t st);
+// FP64 self blocks of the finest boxes (row-major nb x nb at off[b], box order).
+hipError_t launch_diag_blocks(const DevGeo& G, const DevBasis& B, const int32_t* box_ptr, const int64_t* off,
+                              int nbox, void* out, double k, double w2e, hipStream_t st);
 // W right-hand-side columns per pass, register groups of at most rc columns.
 template <typename TN>
 hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part, int W, int rc,
@@ -78,6 +81,11 @@ hipError_t launch_axpy_cols(void* x, const void* y, const void* a, int N, int R,
 hipError_t launch_sub(const void* a, const void* b, int N, int R, void* out, hipStream_t st);
 // Charge equation (pulse-pulse block): b <- RWG rows cleared, pulse rows
 // times (cre + i cim); rho = i weps0 na - eps0 sigma, n entries.
+// Block-diagonal preconditioner y = Minv (x / d) through the box permutation,
+// and x += t / d.
+hipError_t launch_block_prec(const void* x, const double* d, const void* minv, const int64_t* off,
+                             const int32_t* box_ptr, const int32_t* perm, int nbox, int R, void* y, hipStream_t st);
+hipError_t launch_add_scaled(void* x, const void* t, const double* d, int N, int R, hipStream_t st);
 hipError_t launch_pulse_rhs(void* b, int E, int N, int R, double cre, double cim, hipStream_t st);
 hipError_t launch_charge_rho(const cx<double>* na, const cx<double>* sigma, int64_t n, double weps0, double eps0,
                              void* rho, hipStream_t st);

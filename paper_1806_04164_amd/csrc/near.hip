@@ -215,6 +215,20 @@ __global__ void __launch_bounds__(256) k_near_fill(DevGeo G, DevBasis B, DevNear
   }
 }
 
+// Self blocks Z_bb of the finest boxes in FP64 (box order, row-major
+// nb x nb at off[b]), for the solver's block-diagonal preconditioner.
+__global__ void __launch_bounds__(256) k_diag_blocks(DevGeo G, DevBasis B, const int32_t* __restrict__ box_ptr,
+                                                     const int64_t* __restrict__ off, cx<double>* __restrict__ out,
+                                                     double k, double w2e) {
+  const int b = blockIdx.x;
+  const int u0 = box_ptr[b], nb = box_ptr[b + 1] - u0;
+  cx<double>* o = out + off[b];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, j = e - i * nb;
+    o[e] = z_entry(G, B, u0 + i, u0 + j, k, w2e);
+  }
+}
+
 // Diagonal entries Z_uu (FP64) for the equilibration of the solver.
 __global__ void k_diag(DevGeo G, DevBasis B, double* diag_abs, double k, double w2e) {
   int u = blockIdx.x * blockDim.x + threadIdx.x;
@@ -514,6 +528,13 @@ template hipError_t launch_near_fill<float>(const DevGeo&, const DevBasis&, cons
                                             double, double, hipStream_t);
 template hipError_t launch_near_fill<double>(const DevGeo&, const DevBasis&, const DevNear&, void*,
                                              double, double, hipStream_t);
+
+hipError_t launch_diag_blocks(const DevGeo& G, const DevBasis& B, const int32_t* box_ptr, const int64_t* off,
+                              int nbox, void* out, double k, double w2e, hipStream_t st) {
+  if (nbox <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diag_blocks, dim3(nbox), dim3(256), 0, st, G, B, box_ptr, off, (cx<double>*)out, k, w2e);
+  return hipGetLastError();
+}
 
 hipError_t launch_diag(const DevGeo& G, const DevBasis& B, double* diag_abs, double k, double w2e,
                        hipStream_t st) {

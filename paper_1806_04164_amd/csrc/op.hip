@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -84,6 +85,10 @@ struct pie_op {
   void* dPart = nullptr;
   void* dXb = nullptr;
   double* dDiagScale = nullptr;  // |Z_uu|^-1/2, canonical order
+  // block-diagonal preconditioner (inverses of the finest boxes' FP64 self
+  // blocks, box order), built on the first solve that asks for it
+  void* dPrec = nullptr;
+  int64_t* dPrecOff = nullptr;
   double *dKhR = nullptr, *dPolR = nullptr, *dAmpR = nullptr, *dDirs = nullptr;
   int64_t ndirs_cap = 0;
   std::vector<void*> allocs;
@@ -1537,7 +1542,7 @@ pie_status pie_farfield_adjoint(pie_op* op, const void* gF, int64_t R, const dou
 void pie_solve_opts_default(pie_solve_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
-  o->version = 1;
+  o->version = 2;
   o->restart = 100;
   o->maxit = 1000;
   o->refine = 1;
@@ -1553,6 +1558,69 @@ namespace {
 // GMRES(m) with CGS2 on the equilibrated operator D Z D for all R columns in
 // lock step; each column keeps its own Hessenberg matrix and rotations and is
 // frozen once its residual estimate meets tol.  xhat (device) is updated.
+// Block-diagonal preconditioner: the finest boxes' self blocks Z_bb in FP64
+// (computed on the device with the near-field entry routine), inverted on
+// the host by Gauss-Jordan elimination with partial pivoting, stored back in
+// place.  Z^H = conj(Z) (Z is symmetric), so the adjoint solve uses the
+// same blocks through its conjugated input and output.
+pie_status build_prec(pie_op* op) {
+  const pie::Tree& t = *op->tree;
+  const int L = op->L;
+  const int nbox = (int)t.lev[L].nb;
+  std::vector<int64_t> off(nbox + 1, 0);
+  for (int b = 0; b < nbox; ++b) {
+    const int64_t nb = (int64_t)(t.box_ptr[b + 1] - t.box_ptr[b]);
+    off[b + 1] = off[b] + nb * nb;
+  }
+  cx<double>* blocks;
+  int64_t* doff;
+  pie_status s;
+  if ((s = dalloc(op, &blocks, (size_t)off[nbox])) || (s = dalloc(op, &doff, (size_t)nbox + 1))) return s;
+  HIPCHK(hipMemcpy(doff, off.data(), (nbox + 1) * sizeof(int64_t), hipMemcpyHostToDevice), "prec offsets");
+  hipError_t e = launch_diag_blocks(geo(op), basis(op), op->NB.box_ptr, doff, nbox, blocks, op->k, op->w2e, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "self blocks");
+  HIPCHK(hipDeviceSynchronize(), "self blocks");
+  std::vector<std::complex<double>> h((size_t)off[nbox]);
+  HIPCHK(hipMemcpy(h.data(), blocks, h.size() * 16, hipMemcpyDeviceToHost), "self blocks copy");
+  std::vector<std::complex<double>> a;
+  std::vector<int> piv;
+  for (int b = 0; b < nbox; ++b) {
+    const int n = (int)(t.box_ptr[b + 1] - t.box_ptr[b]);
+    std::complex<double>* M = h.data() + off[b];
+    // [M | I] -> [I | M^-1], row pivoting
+    a.assign((size_t)n * 2 * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < n; ++j) a[(size_t)i * 2 * n + j] = M[(size_t)i * n + j];
+      a[(size_t)i * 2 * n + n + i] = 1.0;
+    }
+    for (int c = 0; c < n; ++c) {
+      int p = c;
+      for (int i = c + 1; i < n; ++i)
+        if (std::abs(a[(size_t)i * 2 * n + c]) > std::abs(a[(size_t)p * 2 * n + c])) p = i;
+      if (!(std::abs(a[(size_t)p * 2 * n + c]) > 0.0)) {
+        set_error("singular self block of a finest box (preconditioner)");
+        return PIE_ERR_UNSUPPORTED;
+      }
+      if (p != c)
+        for (int j = 0; j < 2 * n; ++j) std::swap(a[(size_t)p * 2 * n + j], a[(size_t)c * 2 * n + j]);
+      const std::complex<double> inv = 1.0 / a[(size_t)c * 2 * n + c];
+      for (int j = 0; j < 2 * n; ++j) a[(size_t)c * 2 * n + j] *= inv;
+      for (int i = 0; i < n; ++i) {
+        if (i == c) continue;
+        const std::complex<double> f = a[(size_t)i * 2 * n + c];
+        if (f == 0.0) continue;
+        for (int j = 0; j < 2 * n; ++j) a[(size_t)i * 2 * n + j] -= f * a[(size_t)c * 2 * n + j];
+      }
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) M[(size_t)i * n + j] = a[(size_t)i * 2 * n + n + j];
+  }
+  HIPCHK(hipMemcpy(blocks, h.data(), h.size() * 16, hipMemcpyHostToDevice), "preconditioner copy");
+  op->dPrec = blocks;
+  op->dPrecOff = doff;
+  return PIE_OK;
+}
+
 // The operator of a solve: mvm flags (3 = near + far, 4 = adjoint) plus
 // SOLVE_PULSE_BLOCK, which applies the pulse-pulse block alone, embedded as
 // diag(0, Z^AA): the RWG rows of the input are cleared before the product
@@ -1569,7 +1637,10 @@ pie_status solve_mvm(pie_op* op, cx<double>* x, cx<double>* y, int64_t R, int fl
 }
 
 pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xhat, int R, const pie_solve_opts& o,
-                              double tol, int mflags, int* iters, hipStream_t st, cx<double>* work) {
+                              double tol, int mflags, bool prec, int* iters, hipStream_t st, cx<double>* work) {
+  // right preconditioning with P = D^-1 Minv D^-1 (Minv: inverses of the
+  // finest boxes' self blocks): A P v = D Z (Minv D^-1 v), xhat += P V y
+  const int nbox = (int)op->tree->lev[op->L].nb;
   const int N = op->N, m = std::max(1, o.restart);
   const size_t NR = (size_t)N * R;
   cx<double>* V = work;                    // (m+1) blocks
@@ -1619,7 +1690,10 @@ pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xh
     for (; j < m && total < o.maxit; ++j) {
       ++total;
       cx<double>* vj = V + (size_t)j * NR;
-      if ((e = launch_scale_rows(vj, op->dDiagScale, N, R, tmp, st)) != hipSuccess) return hip_fail(e, "scale");
+      e = prec ? launch_block_prec(vj, op->dDiagScale, op->dPrec, op->dPrecOff, op->NB.box_ptr, op->dPerm, nbox, R,
+                                   tmp, st)
+               : launch_scale_rows(vj, op->dDiagScale, N, R, tmp, st);
+      if (e != hipSuccess) return hip_fail(e, "scale");
       if ((s = solve_mvm(op, tmp, w, R, mflags, st))) return s;
       if ((e = launch_scale_rows(w, op->dDiagScale, N, R, w, st)) != hipSuccess) return hip_fail(e, "scale");
       // classical Gram-Schmidt, twice
@@ -1639,11 +1713,14 @@ pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xh
         std::complex<double>* Hr = &H[(size_t)r * (m + 1) * m];
         for (int i = 0; i <= j; ++i) Hr[(size_t)i * m + j] = h[(size_t)i * R + r] + h2[(size_t)i * R + r];
         Hr[(size_t)(j + 1) * m + j] = nrm[r];
+        // complex Givens rotations G_i = [[conj(c), conj(s)], [-s, c]] with
+        // c = a / |(a, b)|, s = b / |(a, b)|, so that G_i (a, b) = (|(a, b)|, 0);
+        // the same G_i is applied to later columns and to g
         for (int i = 0; i < j; ++i) {
           std::complex<double> c = cs[(size_t)r * m + i], sN = sn[(size_t)r * m + i];
           std::complex<double> a = Hr[(size_t)i * m + j], b = Hr[(size_t)(i + 1) * m + j];
-          Hr[(size_t)i * m + j] = c * a + sN * b;
-          Hr[(size_t)(i + 1) * m + j] = -std::conj(sN) * a + std::conj(c) * b;
+          Hr[(size_t)i * m + j] = std::conj(c) * a + std::conj(sN) * b;
+          Hr[(size_t)(i + 1) * m + j] = -sN * a + c * b;
         }
         std::complex<double> a = Hr[(size_t)j * m + j], b = Hr[(size_t)(j + 1) * m + j];
         double den = std::sqrt(std::norm(a) + std::norm(b));
@@ -1653,7 +1730,7 @@ pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xh
         Hr[(size_t)j * m + j] = den;
         Hr[(size_t)(j + 1) * m + j] = 0.0;
         std::complex<double>* gr = &g[(size_t)r * (m + 1)];
-        gr[j + 1] = -std::conj(sN) * gr[j];
+        gr[j + 1] = -sN * gr[j];
         gr[j] = std::conj(c) * gr[j];
         kused[r] = j + 1;
         active[r] = std::abs(gr[j + 1]) > tol * rhn[r];
@@ -1685,7 +1762,17 @@ pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xh
     for (int r = 0; r < R; ++r) kmax = std::max(kmax, kused[r]);
     if (kmax > 0) {
       HIPCHK(hipMemcpyAsync(dh, y.data(), (size_t)kmax * R * 16, hipMemcpyHostToDevice, st), "y copy");
-      if ((e = launch_update(xhat, V, NR, kmax, dh, N, R, st)) != hipSuccess) return hip_fail(e, "update");
+      if (!prec) {
+        if ((e = launch_update(xhat, V, NR, kmax, dh, N, R, st)) != hipSuccess) return hip_fail(e, "update");
+      } else {
+        // tmp = V y; w = Minv D^-1 tmp; xhat += D^-1 w
+        HIPCHK(hipMemsetAsync(tmp, 0, NR * 16, st), "zero");
+        if ((e = launch_update(tmp, V, NR, kmax, dh, N, R, st)) != hipSuccess) return hip_fail(e, "update");
+        if ((e = launch_block_prec(tmp, op->dDiagScale, op->dPrec, op->dPrecOff, op->NB.box_ptr, op->dPerm, nbox, R,
+                                   w, st)) != hipSuccess)
+          return hip_fail(e, "preconditioner");
+        if ((e = launch_add_scaled(xhat, w, op->dDiagScale, N, R, st)) != hipSuccess) return hip_fail(e, "update");
+      }
     }
     HIPCHK(hipStreamSynchronize(st), "gmres");
   }
@@ -1704,16 +1791,23 @@ static pie_status solve_core(pie_op* op, pie_op* res_op, const void* b, void* x,
   pie_solve_opts o;
   pie_solve_opts_default(&o);
   if (opts) {
-    if (opts->version != 1) {
-      pie::set_error("pie_solve_opts.version must be 1");
+    if (opts->version == 1) {
+      std::memcpy(&o, opts, offsetof(pie_solve_opts, precond));  // the fields of version 1
+      o.version = 1;
+      o.precond = 0;
+    } else if (opts->version == 2) {
+      o = *opts;
+    } else {
+      pie::set_error("pie_solve_opts.version must be 1 or 2");
       return PIE_ERR_ARG;
     }
-    o = *opts;
   }
-  if (o.restart < 1 || o.maxit < 1 || o.refine < 1 || !(o.tol > 0.0)) {
-    pie::set_error("restart, maxit, refine must be >= 1 and tol > 0");
+  if (o.restart < 1 || o.maxit < 1 || o.refine < 1 || !(o.tol > 0.0) || (o.precond != 0 && o.precond != 1)) {
+    pie::set_error("restart, maxit, refine must be >= 1, tol > 0 and precond 0 or 1");
     return PIE_ERR_ARG;
   }
+  const bool prec = o.precond == 1 && !block;
+  if (prec && !op->dPrec && (s = build_prec(op))) return s;
   pie_op* rop = res_op ? res_op : op;
   if (rop->N != op->N || R > rop->max_rhs) {
     pie::set_error("residual operator does not match");
@@ -1754,7 +1848,8 @@ static pie_status solve_core(pie_op* op, pie_op* res_op, const void* b, void* x,
     if ((e = pie::launch_scale_rows(rr, op->dDiagScale, N, (int)R, rhat, st)) != hipSuccess) return hip_fail(e, "scale");
     HIPCHK(hipMemsetAsync(xh, 0, NR * 16, st), "zero");
     int it = 0;
-    if ((s = gmres_equilibrated(op, rhat, xh, (int)R, o, inner, 3 | (o.adjoint ? 4 : 0) | block, &it, st, work)))
+    if ((s = gmres_equilibrated(op, rhat, xh, (int)R, o, inner, 3 | (o.adjoint ? 4 : 0) | block, prec, &it, st,
+                                work)))
       return s;
     iters += it;
     if ((e = pie::launch_scale_rows(xh, op->dDiagScale, N, (int)R, xh, st)) != hipSuccess) return hip_fail(e, "scale");
@@ -1783,6 +1878,17 @@ static pie_status solve_core(pie_op* op, pie_op* res_op, const void* b, void* x,
 extern "C" pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void* x, int64_t R,
                                 const pie_solve_opts* opts, pie_solve_info* info, void* stream) {
   return solve_core(op, res_op, b, x, R, opts, info, stream, 0);
+}
+
+extern "C" pie_status pie_precond_apply(pie_op* op, const void* x, void* y, int64_t R, void* stream) {
+  pie_status s = check_op_call(op, x, y, R);
+  if (s) return s;
+  if (!op->dPrec && (s = build_prec(op))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_block_prec(x, nullptr, op->dPrec, op->dPrecOff, op->NB.box_ptr, op->dPerm,
+                                   (int)op->tree->lev[op->L].nb, (int)R, y, st);
+  if (e != hipSuccess) return hip_fail(e, "preconditioner");
+  return PIE_OK;
 }
 
 extern "C" pie_status pie_charge(pie_op* op, int64_t R, const double* khat, const double* pol, const double* amp,
@@ -1817,8 +1923,19 @@ extern "C" pie_status pie_charge(pie_op* op, int64_t R, const double* khat, cons
   if (e != hipSuccess) return hip_fail(e, "charge rhs");
   pie_solve_opts o;
   pie_solve_opts_default(&o);
-  if (opts) o = *opts;
+  if (opts) {
+    if (opts->version == 1) {
+      std::memcpy(&o, opts, offsetof(pie_solve_opts, precond));
+    } else if (opts->version == 2) {
+      o = *opts;
+    } else {
+      pie::set_error("pie_solve_opts.version must be 1 or 2");
+      return PIE_ERR_ARG;
+    }
+  }
+  o.version = 2;
   o.use_x0 = 0;
+  o.precond = 0;  // the self blocks are those of the whole operator
   s = solve_core(op, nullptr, b, X, R, &o, info, stream, SOLVE_PULSE_BLOCK);
   if (s != PIE_OK && s != PIE_WARN_NOT_CONVERGED) return s;
   // sigma = pulse rows of the block solution; rho = i w eps0 (n.A) - eps0 sigma

@@ -272,13 +272,14 @@ class Operator:
         return b
 
     def solve(self, b, x=None, res_op=None, tol=1e-6, restart=100, maxit=1000, refine=1,
-              inner_tol=0.0, adjoint=False, stream=None):
+              inner_tol=0.0, adjoint=False, precond=False, stream=None):
         import torch
         R = self._R(b)
         o = _lib.pie_solve_opts()
         lib().pie_solve_opts_default(ctypes.byref(o))
         o.tol, o.restart, o.maxit, o.refine, o.inner_tol = tol, restart, maxit, refine, inner_tol
         o.adjoint = int(adjoint)
+        o.precond = int(precond)
         o.use_x0 = 0 if x is None else 1
         if x is None:
             x = torch.zeros_like(b)
@@ -288,6 +289,15 @@ class Operator:
         check(st)
         return x, {"iterations": info.iterations, "refinements": info.refinements,
                    "rel_residual": info.rel_residual, "converged": st == 0}
+
+    def precond_apply(self, x, y=None, stream=None):
+        """pie_precond_apply: y = blockdiag(Z_bb)^-1 x."""
+        import torch
+        R = self._R(x)
+        if y is None:
+            y = torch.empty_like(x)
+        check(lib().pie_precond_apply(self.h, _dev(x, self.N, R), _dev(y, self.N, R), R, _stream(stream)))
+        return y
 
     def charge(self, khat, pol, amp, x=None, gauge=0, tol=1e-6, restart=100, maxit=1000, refine=1,
                inner_tol=0.0, stream=None):

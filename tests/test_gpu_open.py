@@ -37,7 +37,7 @@ FREQS = (1e6, 1e8)
 # stalls near 2e-5, so the low-frequency solves stop at 1e-4.  On the
 # paper's patch at 100 MHz the 6-level refinement levels off near 3e-5 (its
 # inner GMRES no longer reaches 1e-3 within 6000 iterations; 5 levels reach
-# 2e-6 in 1800), so the level sweep stops at 1e-4 at both frequencies.
+# 2.3e-6 in 263), so the level sweep stops at 1e-4 at both frequencies.
 TOL = {1e6: 1e-4, 1e8: 1e-7}
 TOL_SWEEP = {1e6: 1e-4, 1e8: 1e-4}
 _TH = np.linspace(0.0, np.pi, 181)

@@ -316,8 +316,10 @@ typedef struct pie_solve_opts {
   int32_t adjoint;    /* 1: solve Z^H x = b                           */
   int32_t precond;    /* 1: right block-diagonal preconditioner: the   */
                       /* inverses of the finest boxes' FP64 self      */
-                      /* blocks (built on the first such solve, kept  */
-                      /* with the operator: 16 sum n_b^2 bytes)       */
+                      /* blocks (built on the first such solve and    */
+                      /* kept with the operator: 16 sum n_b^2 bytes   */
+                      /* of device memory; the inversion runs on the  */
+                      /* host, O(sum n_b^3), one thread)              */
 } pie_solve_opts;
 typedef struct pie_solve_info {
   int32_t iterations; /* total inner iterations (max over RHS)        */

@@ -7,6 +7,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -1582,39 +1583,53 @@ pie_status build_prec(pie_op* op) {
   HIPCHK(hipDeviceSynchronize(), "self blocks");
   std::vector<std::complex<double>> h((size_t)off[nbox]);
   HIPCHK(hipMemcpy(h.data(), blocks, h.size() * 16, hipMemcpyDeviceToHost), "self blocks copy");
-  std::vector<std::complex<double>> a;
-  std::vector<int> piv;
-  for (int b = 0; b < nbox; ++b) {
-    const int n = (int)(t.box_ptr[b + 1] - t.box_ptr[b]);
-    std::complex<double>* M = h.data() + off[b];
-    // [M | I] -> [I | M^-1], row pivoting
-    a.assign((size_t)n * 2 * n, 0.0);
-    for (int i = 0; i < n; ++i) {
-      for (int j = 0; j < n; ++j) a[(size_t)i * 2 * n + j] = M[(size_t)i * n + j];
-      a[(size_t)i * 2 * n + n + i] = 1.0;
-    }
-    for (int c = 0; c < n; ++c) {
-      int p = c;
-      for (int i = c + 1; i < n; ++i)
-        if (std::abs(a[(size_t)i * 2 * n + c]) > std::abs(a[(size_t)p * 2 * n + c])) p = i;
-      if (!(std::abs(a[(size_t)p * 2 * n + c]) > 0.0)) {
-        set_error("singular self block of a finest box (preconditioner)");
-        return PIE_ERR_UNSUPPORTED;
-      }
-      if (p != c)
-        for (int j = 0; j < 2 * n; ++j) std::swap(a[(size_t)p * 2 * n + j], a[(size_t)c * 2 * n + j]);
-      const std::complex<double> inv = 1.0 / a[(size_t)c * 2 * n + c];
-      for (int j = 0; j < 2 * n; ++j) a[(size_t)c * 2 * n + j] *= inv;
+  // Gauss-Jordan [M | I] -> [I | M^-1] with row pivoting, box b of
+  // [b0, nbox) in steps of `step`; false on a singular block
+  auto invert = [&](int b0, int step) {
+    std::vector<std::complex<double>> a;
+    for (int b = b0; b < nbox; b += step) {
+      const int n = (int)(t.box_ptr[b + 1] - t.box_ptr[b]);
+      std::complex<double>* M = h.data() + off[b];
+      a.assign((size_t)n * 2 * n, 0.0);
       for (int i = 0; i < n; ++i) {
-        if (i == c) continue;
-        const std::complex<double> f = a[(size_t)i * 2 * n + c];
-        if (f == 0.0) continue;
-        for (int j = 0; j < 2 * n; ++j) a[(size_t)i * 2 * n + j] -= f * a[(size_t)c * 2 * n + j];
+        for (int j = 0; j < n; ++j) a[(size_t)i * 2 * n + j] = M[(size_t)i * n + j];
+        a[(size_t)i * 2 * n + n + i] = 1.0;
       }
+      for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int i = c + 1; i < n; ++i)
+          if (std::abs(a[(size_t)i * 2 * n + c]) > std::abs(a[(size_t)p * 2 * n + c])) p = i;
+        if (!(std::abs(a[(size_t)p * 2 * n + c]) > 0.0)) return false;
+        if (p != c)
+          for (int j = 0; j < 2 * n; ++j) std::swap(a[(size_t)p * 2 * n + j], a[(size_t)c * 2 * n + j]);
+        const std::complex<double> inv = 1.0 / a[(size_t)c * 2 * n + c];
+        for (int j = 0; j < 2 * n; ++j) a[(size_t)c * 2 * n + j] *= inv;
+        for (int i = 0; i < n; ++i) {
+          if (i == c) continue;
+          const std::complex<double> f = a[(size_t)i * 2 * n + c];
+          if (f == 0.0) continue;
+          for (int j = 0; j < 2 * n; ++j) a[(size_t)i * 2 * n + j] -= f * a[(size_t)c * 2 * n + j];
+        }
+      }
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) M[(size_t)i * n + j] = a[(size_t)i * 2 * n + n + j];
     }
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) M[(size_t)i * n + j] = a[(size_t)i * 2 * n + n + j];
+    return true;
+  };
+  // boxes are independent: strided over up to 16 host threads
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<char> ok(nth, 1);
+  {
+    std::vector<std::thread> pool;
+    for (int i = 1; i < nth; ++i) pool.emplace_back([&, i] { ok[i] = invert(i, nth); });
+    ok[0] = invert(0, nth);
+    for (auto& th : pool) th.join();
   }
+  for (char o : ok)
+    if (!o) {
+      set_error("singular self block of a finest box (preconditioner)");
+      return PIE_ERR_UNSUPPORTED;
+    }
   HIPCHK(hipMemcpy(blocks, h.data(), h.size() * 16, hipMemcpyHostToDevice), "preconditioner copy");
   op->dPrec = blocks;
   op->dPrecOff = doff;

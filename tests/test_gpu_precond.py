@@ -99,3 +99,32 @@ def test_preconditioned_low_frequency():
         print("sphere 12 800, 1e-3 wavelength", "precond" if pc else "plain", info, flush=True)
         res[pc] = info["rel_residual"]
     assert res[True] <= res[False]
+
+
+def test_version_1_options():
+    """A caller built against the first options layout (no precond field,
+    version 1) gets the unpreconditioned solve, bit for bit."""
+    import ctypes
+
+    from paper_1806_04164_amd import _lib
+
+    class OptsV1(ctypes.Structure):
+        _fields_ = [("version", ctypes.c_int32), ("restart", ctypes.c_int32),
+                    ("maxit", ctypes.c_int32), ("refine", ctypes.c_int32), ("tol", ctypes.c_double),
+                    ("inner_tol", ctypes.c_double), ("use_x0", ctypes.c_int32),
+                    ("adjoint", ctypes.c_int32)]
+
+    V, T = synth.icosphere(2)
+    op, keep = _op(V, T, 0.1 * synth.C0 / synth.DIAMETER, 3)
+    b = op.rhs_planewave(*synth.axial_wave())
+    x2, _ = op.solve(b, tol=1e-6, restart=100, maxit=500)
+    o = OptsV1(1, 100, 500, 1, 1e-6, 0.0, 0, 0)
+    x1 = torch.zeros_like(b)
+    info = _lib.pie_solve_info()
+    L = _lib.lib()
+    f = L.pie_solve
+    st = f(op.h, None, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x1.data_ptr()), 1,
+           ctypes.cast(ctypes.byref(o), ctypes.POINTER(_lib.pie_solve_opts)), ctypes.byref(info), None)
+    torch.cuda.synchronize()
+    assert st == 0
+    assert torch.equal(x1, x2)

@@ -8,6 +8,10 @@ lambda/500 and lambda/5).  Boundary edges carry no RWG function; the pulse
   operators, <= 1e-3 (the diagonalisation's truncation error); the GMRES
   solution's far field against the dense LU solution (<= 1e-3) and the
   3-level against the 4-level far field.
+* the adjoint Z^H on the 16 x 16 patch against the dense conj(Z)^T;
+* 16-20 right-hand sides of the paper's patch in one pass (the batched
+  matrix-core kernels on a flat scatterer) against single-column MVMs and
+  sampled oracle rows;
 * the paper's patch (75 x 75 squares, 11 250 triangles, 16 725 RWG):
   sampled rows of the dense oracle against the 5- and 6-level mixed MVM
   (graph replay) <= 1e-3, and the paper's level-consistency experiment: far-zone
@@ -163,3 +167,49 @@ def test_paper_patch_level_consistency(p75, f):
           "5 vs 6 levels: relative far-field difference", rel, "max |dB difference| within 20 dB of the peak",
           d, flush=True)
     assert rel < 2e-3 and d < 0.02
+
+
+def test_patch_adjoint_against_dense(p16):
+    """Z^H y on the open patch: against the dense conj(Z)^T y (1e-3, the
+    diagonalisation's error), and exactly conj(Z conj(y)) of the same
+    operator."""
+    op = _op(p16, 3)
+    y = synth.complex_gaussian(op.N, 1, 13)
+    a = host(op.matvec(dev(y), adjoint=True))[:, 0]
+    b = np.conj(host(op.matvec(dev(np.conj(y))))[:, 0])
+    assert np.array_equal(a, b)
+    ref = np.conj(p16["Z"]).T @ y[:, 0]
+    err = np.linalg.norm(a - ref) / np.linalg.norm(ref)
+    print("patch 16", p16["f"], "adjoint vs dense", err, flush=True)
+    assert err <= 1e-3
+
+
+def test_paper_patch_batched_passes(p75):
+    """16 right-hand sides of the paper's patch in one pass: the batched
+    kernels (matrix-core near field, aggregation, reception and shifts,
+    sibling-group translation) on a flat scatterer whose boxes lie on box
+    faces.  A column equals itself bit for bit in any pass of >= 16
+    columns, matches its single-column MVM to the FP64 rounding carried
+    through the translations (< 2e-4, as on the sphere), and its sampled
+    oracle rows to 1e-3."""
+    f = 1e8
+    R = 16
+    op = pie.Operator(p75["mesh"], p75["trees"][5], f, near_prec=PIE_FP32, far_prec=PIE_FP64, max_rhs=20)
+    N, E = op.N, p75["E"]
+    x = synth.complex_gaussian(N, 20, 91)
+    y20 = host(op.matvec(dev(x)))
+    y16 = host(op.matvec(dev(x[:, 2:18].copy())))
+    assert np.array_equal(y20[:, 2:18], y16)
+    for r in (0, 11, 19):
+        y1 = host(op.matvec(dev(x[:, r:r + 1].copy())))[:, 0]
+        d = np.linalg.norm(y20[:, r] - y1) / np.linalg.norm(y1)
+        print("patch 75 batched vs single column", r, d, flush=True)
+        assert d < 2e-4
+    rng = np.random.default_rng(12)
+    rows = np.sort(np.concatenate([rng.choice(E, 4, replace=False), E + rng.choice(N - E, 4, replace=False)]))
+    ref = sampled_rows([(("patch", 75), f, rows, 91, 20)])[0]
+    yr = y20[rows]
+    full = ref["J"] + ref["A"]
+    err = np.linalg.norm(yr - full) / np.linalg.norm(full)
+    print("patch 75 batched vs oracle rows", err, flush=True)
+    assert err <= 1e-3

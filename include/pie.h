@@ -319,7 +319,10 @@ typedef struct pie_solve_opts {
                       /* blocks (built on the first such solve and    */
                       /* kept with the operator: 16 sum n_b^2 bytes   */
                       /* of device memory; the inversion runs on the  */
-                      /* host, O(sum n_b^3), up to 16 threads)        */
+                      /* host, O(sum n_b^3), up to 16 threads).       */
+                      /* Suited to open surfaces; on closed surfaces  */
+                      /* a box's local charge modes make M^-1 huge    */
+                      /* and it slows or stalls GMRES                 */
 } pie_solve_opts;
 typedef struct pie_solve_info {
   int32_t iterations; /* total inner iterations (max over RHS)        */

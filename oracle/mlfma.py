@@ -2,7 +2,8 @@
 
 Steps, in the paper's order for one MVM:
   near field   y = Z_near x, the exact matrix entries of Eqs. (1)-(2) for
-               basis pairs in near finest-level boxes;
+               basis functions (RWG part) and triangles (scalar part) in near
+               finest-level boxes;
   aggregation  radiation patterns of every finest box, then shifted up to
                coarser levels (down to level 3);
   translation  at every level l >= 3, diagonal (per direction) products of
@@ -11,6 +12,9 @@ Steps, in the paper's order for one MVM:
                Eq. (4);
   disaggregation  incoming patterns shifted down to the finest level, then
                received by the testing functions and added to y.
+How the blocks of Z are split between near and far interactions (the
+scalar operator per triangle, the vector part per RWG function) is stated
+in the class docstring.
 
 Eq. (4) with r - r' = w + v, w = C_obs - C_src, v = (r - C_obs) - (r' - C_src),
 kappa = k/s:
@@ -121,7 +125,26 @@ def interlevel_filter(khat, w, tau, ratio):
 
 
 class MLFMA:
-    """One operator: mesh + frequency + tree + parameters."""
+    """One operator: mesh + frequency + tree + parameters.
+
+    Near/far split.  With S_qp = <P_q, int P_p g> (the pulse-pulse Galerkin
+    matrix of g) and the divergence matrix G[m, t] = div f_m on triangle t
+    (+-l/A), the blocks of Eqs. (1)-(2) after the by-parts step of Section 3
+    are Z^JA = G S, Z^AJ = S G^T and Z^AA = w^2 eps0 S: one scalar operator
+    acting on sigma = x_A (for the RWG rows) and on u = G^T x_J + w^2 eps0 x_A
+    (for the pulse rows).  The paper does not say how basis functions are
+    split between near and far interactions; here the split keeps that
+    identity for the approximation too:
+      * S is applied per triangle: each triangle radiates and receives at the
+        finest box of its centroid (the box of its pulse), and a triangle
+        pair is near when those boxes are neighbours;
+      * the vector part mu0 <f_m, int f_n g> is applied per RWG function,
+        both halves at the finest box of its edge midpoint, near when the
+        two RWG boxes are neighbours.
+    Then Z_mlfma = [[mu0 L~, G S~], [S~ G^T, w^2 eps0 S~]] exactly, so the
+    divergence-free (loop) currents give no scalar source and the charge
+    vector with S~ b = const * area is annihilated by the JA block, as for the
+    dense matrix; only the 7-point-rule moments and Eqs. (4)-(5) differ."""
 
     def __init__(self, prob: _mom.Problem, L: int, params: Params = Params()):
         self.prob = prob
@@ -150,99 +173,179 @@ class MLFMA:
         for l in range(3, L):
             self.F[l] = interlevel_filter(self.khat, self.w, params.tau,
                                           self.kappa[l] / self.kappa[l + 1])
+        m = prob.mesh
+        self.E = m.nE
+        self.tri_box = tr.box_of[m.nE:]      # finest box of each triangle (its pulse's box)
+        # G as two entries per RWG row: triangle and divergence +-l/A
+        self.g_tri = m.tri                               # [E,2]
+        self.g_div = np.stack([m.length / m.area[m.tri[:, 0]],
+                               -m.length / m.area[m.tri[:, 1]]], axis=1)
         self._near = None
 
     # ------------------------------------------------------------------
-    # radiation patterns of the basis functions at the finest level
+    # the divergence matrix G and its transpose
     # ------------------------------------------------------------------
-    def basis_patterns(self, idx):
-        """For canonical unknowns ``idx``: (F [n,Q,3], D [n,Q]) for RWG
-        (vector pattern and divergence pattern), P [n,Q] for pulses (in D's
-        slot, F zero), about the finest box centre, at kappa_L:
-            F_n(q) = int f_n(r') exp(-i kappa khat_q.(r' - C)) dr'."""
+    def div_sources(self, xJ):
+        """G^T x_J: the divergence of the current on each triangle [T,R]."""
+        m = self.prob.mesh
+        out = np.zeros((m.nT, xJ.shape[1]), dtype=np.complex128)
+        for h in range(2):
+            np.add.at(out, self.g_tri[:, h], self.g_div[:, h, None] * xJ)
+        return out
+
+    def div_test(self, phi):
+        """G phi: the divergence of each RWG tested against a per-triangle
+        potential phi [T,R] -> [E,R]."""
+        return self.g_div[:, 0, None] * phi[self.g_tri[:, 0]] + self.g_div[:, 1, None] * phi[self.g_tri[:, 1]]
+
+    # ------------------------------------------------------------------
+    # radiation patterns at the finest level
+    # ------------------------------------------------------------------
+    def rwg_patterns(self, e):
+        """Vector patterns F_n(q) = int f_n(r') exp(-i kappa khat_q.(r' - C)) dr'
+        [n,Q,3] of RWG functions e about their boxes' centres, at kappa_L."""
         pr = self.prob
         m = pr.mesh
         tr = self.tree
-        L = self.L
-        idx = np.asarray(idx, dtype=np.int64)
-        C = tr.levels[L].centre[tr.box_of[idx]]
-        kap = self.kappa[L]
-        F = np.zeros((idx.size, self.Q, 3), dtype=np.complex128)
-        D = np.zeros((idx.size, self.Q), dtype=np.complex128)
-        isr = idx < m.nE
-        e = idx[isr]
+        e = np.asarray(e, dtype=np.int64)
+        C = tr.levels[self.L].centre[tr.box_of[e]]
+        kap = self.kappa[self.L]
+        F = np.zeros((e.size, self.Q, 3), dtype=np.complex128)
         for h, sgn in ((0, 1.0), (1, -1.0)):
             t = m.tri[e, h]
             P = pr.P[t]                                            # [n,7,3]
-            W = pr.W[t]
-            ph = np.exp(-1j * kap * np.einsum("nid,qd->niq", P - C[isr][:, None, :], self.khat))
+            ph = np.exp(-1j * kap * np.einsum("nid,qd->niq", P - C[:, None, :], self.khat))
             fv = (sgn * m.length[e] / (2.0 * m.area[t]))[:, None, None] * (
                 P - m.V[m.free[e, h]][:, None, :])
-            F[isr] += np.einsum("ni,nid,niq->nqd", W, fv, ph)
-            D[isr] += (sgn * m.length[e] / m.area[t])[:, None] * np.einsum("ni,niq->nq", W, ph)
-        tp = idx[~isr] - m.nE
-        P = pr.P[tp]
-        ph = np.exp(-1j * kap * np.einsum("nid,qd->niq", P - C[~isr][:, None, :], self.khat))
-        D[~isr] = np.einsum("ni,niq->nq", pr.W[tp], ph)
-        return F, D
+            F += np.einsum("ni,nid,niq->nqd", pr.W[t], fv, ph)
+        return F
+
+    def tri_patterns(self, t):
+        """Scalar patterns P_t(q) = int_t exp(-i kappa khat_q.(r' - C)) dr' [n,Q]
+        of triangles t about their own boxes' centres, at kappa_L."""
+        pr = self.prob
+        t = np.asarray(t, dtype=np.int64)
+        C = self.tree.levels[self.L].centre[self.tri_box[t]]
+        ph = np.exp(-1j * self.kappa[self.L] * np.einsum("nid,qd->niq", pr.P[t] - C[:, None, :], self.khat))
+        return np.einsum("ni,niq->nq", pr.W[t], ph)
 
     # ------------------------------------------------------------------
+    # near field
+    # ------------------------------------------------------------------
     def near_matrix(self):
-        """Near-field entries per finest box row: list of (rows, cols, block)."""
+        """Near-field blocks per finest box: (RWG rows, RWG cols, mu0 L block)
+        and (triangle rows, triangle cols, S block)."""
         if self._near is None:
+            pr = self.prob
             tr = self.tree
-            blocks = []
-            nb = tr.box_ptr.size - 1
-            for b in range(nb):
-                rows = tr.perm[tr.box_ptr[b]:tr.box_ptr[b + 1]]
+            E = self.E
+            w2e = pr.omega ** 2 * _mom.EPS0
+            JJ, SS = [], []
+            for b in range(tr.box_ptr.size - 1):
+                u = tr.perm[tr.box_ptr[b]:tr.box_ptr[b + 1]]
                 nbrs = tr.near_idx[tr.near_ptr[b]:tr.near_ptr[b + 1]]
                 cols = np.concatenate([tr.perm[tr.box_ptr[j]:tr.box_ptr[j + 1]] for j in nbrs])
-                blocks.append((rows, cols, self.prob.zblock(rows, cols)))
-            self._near = blocks
+                rj, cj = u[u < E], cols[cols < E]
+                rt, ct = u[u >= E], cols[cols >= E]
+                JJ.append((rj, cj, pr.zblock(rj, cj)))
+                SS.append((rt - E, ct - E, pr.zblock(rt, ct) / w2e))
+            self._near = (JJ, SS)
         return self._near
+
+    def near(self, x):
+        """Near-field part Z_near x; x [N] or [N,R] canonical order."""
+        x = np.asarray(x, dtype=np.complex128)
+        one = x.ndim == 1
+        if one:
+            x = x[:, None]
+        E = self.E
+        w2e = self.prob.omega ** 2 * _mom.EPS0
+        xJ, xA = x[:E], x[E:]
+        u = self.div_sources(xJ) + w2e * xA
+        JJ, SS = self.near_matrix()
+        yJ = np.zeros(xJ.shape, dtype=np.complex128)
+        phi = np.zeros(xA.shape, dtype=np.complex128)
+        psi = np.zeros(xA.shape, dtype=np.complex128)
+        for r, c, blk in JJ:
+            yJ[r] += blk @ xJ[c]
+        for r, c, blk in SS:
+            phi[r] += blk @ xA[c]
+            psi[r] += blk @ u[c]
+        y = np.concatenate([yJ + self.div_test(phi), psi], axis=0)
+        return y[:, 0] if one else y
 
     def near_rows(self, rows):
         """Near-field rows (canonical indices) as a dense [len(rows), N]."""
+        pr = self.prob
         tr = self.tree
-        out = np.zeros((len(rows), self.prob.N), dtype=np.complex128)
-        for i, r in enumerate(rows):
-            b = tr.box_of[r]
+        E = self.E
+        w2e = pr.omega ** 2 * _mom.EPS0
+        out = np.zeros((len(rows), pr.N), dtype=np.complex128)
+
+        def near_cols(unk, kind):
+            b = tr.box_of[unk]
             nbrs = tr.near_idx[tr.near_ptr[b]:tr.near_ptr[b + 1]]
             cols = np.concatenate([tr.perm[tr.box_ptr[j]:tr.box_ptr[j + 1]] for j in nbrs])
-            out[i, cols] = self.prob.zblock([r], cols)[0]
+            return cols[cols < E] if kind == "J" else cols[cols >= E]
+
+        def s_row(t):
+            """Near row of S for triangle t: (triangle cols, values)."""
+            ct = np.sort(near_cols(E + t, "A"))
+            return ct - E, pr.zblock([E + t], ct)[0] / w2e
+
+        for i, r in enumerate(rows):
+            if r < E:
+                cj = near_cols(r, "J")
+                out[i, cj] = pr.zblock([r], cj)[0]
+                for h in range(2):                      # G S_near x_A
+                    tc, sv = s_row(self.g_tri[r, h])
+                    out[i, E + tc] += self.g_div[r, h] * sv
+            else:
+                tc, sv = s_row(r - E)                   # S_near (G^T x_J + w2e x_A)
+                out[i, E + tc] += w2e * sv
+                for h in range(2):
+                    hit = np.isin(self.g_tri[:, h], tc)
+                    e = np.nonzero(hit)[0]
+                    pos = np.searchsorted(tc, self.g_tri[e, h])
+                    np.add.at(out[i], e, self.g_div[e, h] * sv[pos])
         return out
 
     # ------------------------------------------------------------------
+    # far field
+    # ------------------------------------------------------------------
     def far(self, x, rows=None):
         """Far-field part of Z x; x [N] or [N,R] canonical order.  If rows
-        is given, only those outputs are formed (the whole upward pass and
+        is given, only those outputs are returned (the whole upward pass and
         translation are still done)."""
         pr = self.prob
         m = pr.mesh
         tr = self.tree
         L = self.L
+        E = self.E
         x = np.asarray(x, dtype=np.complex128)
         one = x.ndim == 1
         if one:
             x = x[:, None]
         R = x.shape[1]
         w2e = pr.omega ** 2 * _mom.EPS0
-        N = pr.N
+        xJ, xA = x[:E], x[E:]
+        u = self.div_sources(xJ) + w2e * xA
         nbL = tr.levels[L].coords.shape[0]
         # --- aggregation at the finest level: components Jx,Jy,Jz,sigma,u
         S = {L: np.zeros((nbL, self.Q, 5, R), dtype=np.complex128)}
-        for c0 in range(0, N, 4096):
-            idx = np.arange(c0, min(N, c0 + 4096))
-            F, D = self.basis_patterns(idx)
-            bx = tr.box_of[idx]
-            isr = idx < m.nE
-            xs = x[idx]
-            contrib = np.zeros((idx.size, self.Q, 5, R), dtype=np.complex128)
-            contrib[isr, :, 0:3, :] = np.einsum("nqd,nr->nqdr", F[isr], xs[isr])
-            contrib[isr, :, 4, :] = np.einsum("nq,nr->nqr", D[isr], xs[isr])
-            contrib[~isr, :, 3, :] = np.einsum("nq,nr->nqr", D[~isr], xs[~isr])
-            contrib[~isr, :, 4, :] = w2e * np.einsum("nq,nr->nqr", D[~isr], xs[~isr])
-            np.add.at(S[L], bx, contrib)
+        for c0 in range(0, E, 4096):
+            e = np.arange(c0, min(E, c0 + 4096))
+            F = self.rwg_patterns(e)
+            contrib = np.zeros((e.size, self.Q, 5, R), dtype=np.complex128)
+            contrib[:, :, 0:3, :] = np.einsum("nqd,nr->nqdr", F, xJ[e])
+            np.add.at(S[L], tr.box_of[e], contrib)
+        for c0 in range(0, m.nT, 4096):
+            t = np.arange(c0, min(m.nT, c0 + 4096))
+            P = self.tri_patterns(t)
+            contrib = np.zeros((t.size, self.Q, 5, R), dtype=np.complex128)
+            contrib[:, :, 3, :] = np.einsum("nq,nr->nqr", P, xA[t])
+            contrib[:, :, 4, :] = np.einsum("nq,nr->nqr", P, u[t])
+            np.add.at(S[L], self.tri_box[t], contrib)
         # --- aggregation up the tree
         for l in range(L - 1, 2, -1):
             lev, ch = tr.levels[l], tr.levels[l + 1]
@@ -271,29 +374,30 @@ class MLFMA:
             ph = np.exp(1j * self.kappa[l] * (dc @ self.khat.T))
             H = ph[:, :, None, None] * G[l][ch.parent]
             G[l + 1] += np.einsum("qp,bqcr->bpcr", self.F[l], H)
-        # --- receive at the finest level
+        # --- receive at the finest level: the scalar potentials of every
+        # triangle, then the RWG and pulse rows
+        phi = np.zeros((m.nT, R), dtype=np.complex128)
+        psi = np.zeros((m.nT, R), dtype=np.complex128)
+        for c0 in range(0, m.nT, 4096):
+            t = np.arange(c0, min(m.nT, c0 + 4096))
+            P = self.tri_patterns(t).conj()
+            Gb = G[L][self.tri_box[t]]
+            phi[t] = np.einsum("nq,nqr->nr", P, Gb[:, :, 3])
+            psi[t] = np.einsum("nq,nqr->nr", P, Gb[:, :, 4])
         if rows is None:
-            rows = np.arange(N)
+            rows = np.arange(pr.N)
         rows = np.asarray(rows, dtype=np.int64)
         y = np.zeros((rows.size, R), dtype=np.complex128)
-        for c0 in range(0, rows.size, 4096):
-            idx = rows[c0:c0 + 4096]
-            F, D = self.basis_patterns(idx)
-            Gb = G[L][tr.box_of[idx]]                                    # [n,Q,5,R]
-            isr = idx < m.nE
-            yy = np.zeros((idx.size, R), dtype=np.complex128)
-            yy[isr] = (_mom.MU0 * np.einsum("nqd,nqdr->nr", F[isr].conj(), Gb[isr][:, :, 0:3])
-                       + np.einsum("nq,nqr->nr", D[isr].conj(), Gb[isr][:, :, 3]))
-            yy[~isr] = np.einsum("nq,nqr->nr", D[~isr].conj(), Gb[~isr][:, :, 4])
-            y[c0:c0 + idx.size] = yy
+        isr = rows < E
+        e = rows[isr]
+        if e.size:
+            F = self.rwg_patterns(e).conj()
+            Gb = G[L][tr.box_of[e]]
+            y[isr] = (_mom.MU0 * np.einsum("nqd,nqdr->nr", F, Gb[:, :, 0:3])
+                      + self.g_div[e, 0, None] * phi[self.g_tri[e, 0]]
+                      + self.g_div[e, 1, None] * phi[self.g_tri[e, 1]])
+        y[~isr] = psi[rows[~isr] - E]
         return y[:, 0] if one else y
-
-    def near(self, x):
-        x = np.asarray(x, dtype=np.complex128)
-        y = np.zeros(x.shape, dtype=np.complex128)
-        for rows, cols, blk in self.near_matrix():
-            y[rows] += blk @ x[cols]
-        return y
 
     def matvec(self, x):
         return self.near(x) + self.far(x)

@@ -86,6 +86,16 @@ struct DevBasis {
   int32_t N, ne;
 };
 
+// The scalar operator's sources per triangle t (canonical order): the RWG
+// functions on its (up to three) edges and their divergence +-l/A on t, so
+// that u_t = div J on t + w^2 eps0 x_A[t] = sum_k d[3t+k] x[e[3t+k]] + w^2 eps0
+// x[ne + t]; e = -1 for an edge without an RWG function (open surfaces).
+struct DevTriDiv {
+  const int32_t* e;  // [nt][3]
+  const double* d;   // [nt][3]
+  int32_t nt, ne;
+};
+
 // Stored near-field blocks (a <= b, Morton box indices), row-major n_a x n_b,
 // processed as row-panel tasks of at most one LDS panel each.
 // One row panel [i0, i0 + nr) of a stored near block (a, b): 32 bytes, so a
@@ -101,7 +111,12 @@ struct NearTaskDesc {
 };
 static_assert(sizeof(NearTaskDesc) == 32, "task descriptor is 8 dwords");
 
+// One block-sparse near-field structure: either the RWG-RWG blocks (entries
+// mu0 <f_m, int f_n g>, slots = the RWG functions in box order) or the
+// triangle-triangle blocks (entries S_qp = <P_q, int P_p g>, slots = the
+// triangles in box order).  Each box's slots are contiguous.
 struct DevNear {
+  int32_t kind;             // 0: RWG-RWG, 1: triangle-triangle
   int32_t nblk;
   const int32_t* blk_a;
   const int32_t* blk_b;
@@ -110,7 +125,8 @@ struct DevNear {
   int32_t ntask;
   const struct NearTaskDesc* tdesc;  // [ntask] one row panel per SpMM work unit
   const int32_t* pcol;      // task -> partial-sum slot of its column sums (a < b)
-  const int32_t* box_ptr;   // [nbL+1] box-order unknown ranges
+  const int32_t* slot_ptr;  // [nbL+1] slot ranges of the boxes
+  const int32_t* ubase;     // [nbL] box-order unknown of each box's first slot
   const int32_t* row_ptr;   // [nbL+1] blocks whose a is the box
   const int32_t* col_ptr;   // [nbL+1] into col_blk
   const int32_t* col_blk;   // tasks of blocks (a < b) whose b is the box
@@ -154,22 +170,23 @@ constexpr int TB_UMAX = 80;
 constexpr int TB_EMAX = 16;
 
 // (finest box, triangle) incidences: up to three RWG functions of the box
-// that live on the triangle, and the triangle's pulse if it is in the box.
-// Geometry is stored relative to the box centre C, so that a thread forms a
-// quadrature point's source density or testing integral from independent
-// loads only.
+// that live on the triangle, and the triangle's pulse if the triangle belongs
+// to the box (its home incidence: the scalar sources sigma and u of the
+// triangle radiate and are received there).  Geometry is stored relative to
+// the box centre C, so that a thread forms a quadrature point's source
+// density or testing integral from independent loads only.
 struct DevInc {
   const int32_t* ptr;   // [nbL+1] incidence range of each finest box
   const double* pw;     // [ninc][7][4] (r_i - C, quadrature weight W_i)
   const int32_t* xc;    // [ninc][4] canonical unknown of RWG slot k < 3 / of the pulse (k = 3), or -1
   const double* rs;     // [ninc][3] +-l/(2A)  (0 for an empty slot)
-  const double* rd;     // [ninc][3] +-l/A     (0 for an empty slot)
   const double* pv;     // [ninc][3][3] free vertex - C (0 for an empty slot)
   // per box-order unknown u and half h (a pulse uses h = 0 only)
   const int32_t* uj;    // [N][2] incidence index
   const double* us;     // [N][2] +-l/(2A)
-  const double* ud;     // [N][2] +-l/A
   const double* upv;    // [N][2][3] free vertex - C
+  const int32_t* uptr;  // [nbL+1] box-order unknown range of each finest box
+  DevTriDiv td;         // divergence sources of the triangles
 };
 
 }  // namespace pie

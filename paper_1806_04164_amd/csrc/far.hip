@@ -28,13 +28,32 @@ constexpr int TSET_MAX = 8;  // levels per multi-level translation launch
 // The sample set is symmetric under khat -> -khat with the antipode of every
 // sample q >= Qh among the first Qh, so M(q) = conj M(anti[q]) and only the
 // first Qh samples are stored (Qh = Q/2; Qh = Q with anti[q] = q otherwise).
-// An RWG half s (r - p) on the triangle radiates s (M1 - (p - C) M0), its
-// divergence d M0 and a pulse M0, so with the incidence coefficients
-//   a = sum_k x_k s_k,  b = sum_k x_k s_k (p_k - C),  xp = x_pulse,
-//   cu = sum_k x_k d_k + w^2 eps0 xp
+// An RWG half s (r - p) on the triangle radiates s (M1 - (p - C) M0); the
+// scalar sources of the triangle radiate from its home incidence only (the
+// box of its centroid): sigma = x_A and u = div J + w^2 eps0 x_A, with div J
+// summed over all the RWG functions on the triangle, wherever they live.
+// So with the incidence coefficients
+//   a = sum_k x_k s_k,  b = sum_k x_k s_k (p_k - C)   (the box's RWG halves),
+//   xp = x_A, cu = u     (home incidence; 0 otherwise)
 // the box patterns are
 //   S_J(q) += a M1 - b M0,  S_sigma(q) += xp M0,  S_u(q) += cu M0.
 // ---------------------------------------------------------------------------
+// u of triangle t for column col (conjugated input for the adjoint).
+__device__ __forceinline__ cx<double> tri_u(const DevTriDiv& td, const cx<double>* __restrict__ x, int ldx,
+                                            int col, int t, cx<double> xa, double w2e, int conjx) {
+  cx<double> u = w2e * xa;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int e = td.e[3 * t + k];
+    if (e >= 0) {
+      cx<double> v = x[(size_t)e * ldx + col];
+      if (conjx) v.im = -v.im;
+      u = u + td.d[3 * t + k] * v;
+    }
+  }
+  return u;
+}
+
 template <typename TF>
 __global__ void __launch_bounds__(128) k_moments(const double* __restrict__ pw, const double* __restrict__ khat,
                                                  int Qh, double kappa, cx<TF>* __restrict__ M) {
@@ -99,11 +118,10 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
       int xc[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) xc[k] = c0 + r < W ? I.xc[4 * j + k] : -1;
-      double sv[3], dv[3], pv[3][3];
+      double sv[3], pv[3][3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         sv[k] = I.rs[3 * j + k];
-        dv[k] = I.rd[3 * j + k];
 #pragma unroll
         for (int c = 0; c < 3; ++c) pv[k][c] = I.pv[9 * j + 3 * k + c];
       }
@@ -113,15 +131,15 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
         xv[k] = xc[k] >= 0 ? x[(size_t)xc[k] * ldx + c0 + r] : mk(0.0, 0.0);
         if (conjx) xv[k].im = -xv[k].im;
       }
-      cx<double> a = mk(0.0, 0.0), bb[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)}, cu = mk(0.0, 0.0);
+      cx<double> a = mk(0.0, 0.0), bb[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         a = a + sv[k] * xv[k];
 #pragma unroll
         for (int c = 0; c < 3; ++c) bb[c] = bb[c] + (sv[k] * pv[k][c]) * xv[k];
-        cu = cu + dv[k] * xv[k];
       }
-      cu = cu + w2e * xv[3];
+      const cx<double> cu =
+          xc[3] >= 0 ? tri_u(I.td, x, ldx, c0 + r, xc[3] - I.td.ne, xv[3], w2e, conjx) : mk(0.0, 0.0);
       cx<TF>* o = cf + (size_t)jl * 6 * RC + r;
       o[0] = mk((TF)a.re, (TF)a.im);
 #pragma unroll
@@ -269,16 +287,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             xv[k] = xi >= 0 ? x[(size_t)xi * ldx + c0 + r] : mk(0.0, 0.0);
             if (conjx) xv[k].im = -xv[k].im;
           }
-          cx<double> a = mk(0.0, 0.0), bb[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)}, cu = mk(0.0, 0.0);
+          cx<double> a = mk(0.0, 0.0), bb[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
-            const double sv = I.rs[3 * j + k], dv = I.rd[3 * j + k];
+            const double sv = I.rs[3 * j + k];
             a = a + sv * xv[k];
 #pragma unroll
             for (int c = 0; c < 3; ++c) bb[c] = bb[c] + (sv * I.pv[9 * j + 3 * k + c]) * xv[k];
-            cu = cu + dv * xv[k];
           }
-          cu = cu + w2e * xv[3];
+          const int xp = I.xc[4 * j + 3];
+          const cx<double> cu =
+              xp >= 0 ? tri_u(I.td, x, ldx, c0 + r, xp - I.td.ne, xv[3], w2e, conjx) : mk(0.0, 0.0);
           v[0] = a;
 #pragma unroll
           for (int c = 0; c < 3; ++c) v[1 + c] = mk(-bb[c].re, -bb[c].im);
@@ -859,22 +878,122 @@ __global__ void __launch_bounds__(512) k_translate_set(TranslateSet ts, int Q, i
 // the moments of each incidence j
 //   A = sum_q conj(M1).G_J,  B = sum_q conj(M0) G_J,
 //   Cs = sum_q conj(M0) G_sigma,  Du = sum_q conj(M0) G_u,
-// an RWG half s (r - p), divergence d, tests to  mu0 s (A - (p - C).B) + d Cs
-// and a pulse to Du.  Thread (incidence, slice of the stored samples) sums
-// its slice, each stored sample s together with its antipode (receiving
-// factors conj M(s) and M(s)); the eight slices are added by a fixed
-// butterfly.  Each unknown
-// then adds its halves, its near-field partial sums in a fixed order (slot
-// lists staged in LDS), and is written to its canonical position
-// (conjugated for the adjoint).
+// an RWG half s (r - p) tests the vector part to mu0 s (A - (p - C).B); at
+// its home incidence a triangle receives phi = Cs (the potential of the
+// sigma sources) and psi = Du (its pulse row).  Thread (incidence, slice of
+// the stored samples) sums its slice, each stored sample s together with
+// its antipode (receiving factors conj M(s) and M(s)); the eight slices are
+// added by a fixed butterfly.  Each unknown then adds its halves, its
+// near-field partial sums in a fixed order (slot lists staged in LDS), and
+// is written to its canonical position (conjugated for the adjoint); phi
+// goes to a per-triangle array for the divergence testing of the RWG rows.
 // ---------------------------------------------------------------------------
+// Near-field partial-sum slots of finest box b in a fixed order: the
+// RWG-RWG structure's row and column slots (nslotJ of them), then the
+// triangle-triangle structure's (nslot in all); staged in LDS.
+__device__ __forceinline__ void near_join_slots(const DevNear& NJ, const DevNear& NT, int b, bool do_near,
+                                                int32_t* slots, int& nslotJ, int& nslot) {
+  const int nrowJ = do_near ? NJ.row_ptr[b + 1] - NJ.row_ptr[b] : 0;
+  nslotJ = do_near ? nrowJ + NJ.col_ptr[b + 1] - NJ.col_ptr[b] : 0;
+  const int nrowT = do_near ? NT.row_ptr[b + 1] - NT.row_ptr[b] : 0;
+  nslot = nslotJ + (do_near ? nrowT + NT.col_ptr[b + 1] - NT.col_ptr[b] : 0);
+  for (int e = threadIdx.x; e < nslot; e += blockDim.x) {
+    if (e < nslotJ)
+      slots[e] = e < nrowJ ? NJ.prow[NJ.row_ptr[b] + e] : NJ.pcol[NJ.col_blk[NJ.col_ptr[b] + e - nrowJ]];
+    else {
+      const int f = e - nslotJ;
+      slots[e] = f < nrowT ? NT.prow[NT.row_ptr[b] + f] : NT.pcol[NT.col_blk[NT.col_ptr[b] + f - nrowT]];
+    }
+  }
+}
+
+// Sum of the near partial sums of one unknown: slots [k0, k1) of the staged
+// list, local index ul in its structure, column col of a [slot][ld] array.
+template <typename TN>
+__device__ __forceinline__ void near_join(const cx<TN>* __restrict__ part, const int32_t* slots, int k0, int k1,
+                                          int ul, int ld, size_t col, cx<double>& val) {
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    cx<TN> v[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) v[tt] = part[((size_t)slots[k + tt] + ul) * ld + col];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      val.re += (double)v[tt].re;
+      val.im += (double)v[tt].im;
+    }
+  }
+  for (; k < k1; ++k) {
+    const cx<TN> v = part[((size_t)slots[k] + ul) * ld + col];
+    val.re += (double)v.re;
+    val.im += (double)v.im;
+  }
+}
+
+// Per-unknown assembly of the reception (both reception kernels): an RWG
+// row gets its halves' vector testing mu0 s (A - (p - C).B) and the
+// RWG-RWG near sums; a triangle (pulse row) gets psi = Du + the S near sums
+// of u, which is its output, and phi = Cs + the S near sums of x_A, the
+// potential that the RWG rows on the triangle test with their divergence
+// (added by k_div_test).  rv(h, o) returns the incidence sum o of half h.
+template <typename TN, typename RV>
+__device__ __forceinline__ void receive_unknown(const DevInc& I, const DevBasis& B, int u, int ul, int nJb, int r,
+                                                int c0, int W, bool do_far, bool do_near, bool conj_out,
+                                                const cx<TN>* __restrict__ partJ, const cx<TN>* __restrict__ partT,
+                                                const int32_t* slots, int nslotJ, int nslot, RV rv,
+                                                cx<double>* __restrict__ y, int ldy, cx<double>* __restrict__ phi) {
+  const double mu0 = 4.0e-7 * 3.14159265358979323846;
+  const int cu = B.perm[u];
+  const size_t col = (size_t)c0 + r;
+  if (cu < B.ne) {
+    cx<double> val = mk(0.0, 0.0);
+    if (do_far) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double sv = I.us[2 * u + h];
+        cx<double> t = rv(h, 0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double pc = I.upv[6 * (size_t)u + 3 * h + c];
+          const cx<double> bc = rv(h, 1 + c);
+          t.re -= pc * bc.re;
+          t.im -= pc * bc.im;
+        }
+        val.re += mu0 * sv * t.re;
+        val.im += mu0 * sv * t.im;
+      }
+    }
+    if (do_near) near_join(partJ, slots, 0, nslotJ, ul, W, col, val);
+    if (conj_out) val.im = -val.im;
+    y[(size_t)cu * ldy + col] = val;
+  } else {
+    cx<double> ph = mk(0.0, 0.0), ps = mk(0.0, 0.0);
+    if (do_far) {
+      ph = rv(0, 4);
+      ps = rv(0, 5);
+    }
+    if (do_near) {
+      const int lt = ul - nJb;
+      near_join(partT, slots, nslotJ, nslot, lt, 2 * W, col, ph);
+      near_join(partT, slots, nslotJ, nslot, lt, 2 * W, (size_t)W + col, ps);
+    }
+    if (conj_out) {
+      ph.im = -ph.im;
+      ps.im = -ps.im;
+    }
+    y[(size_t)cu * ldy + col] = ps;
+    phi[(size_t)(cu - B.ne) * W + col] = ph;
+  }
+}
+
 constexpr int RECV_SLICES = 8;  // lanes per incidence (a power of two)
 template <typename TF, typename TN, int RC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 1 ? 4 : 1))) k_receive(DevInc I, DevBasis B, DevNear NB, int nbox,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 1 ? 4 : 1))) k_receive(DevInc I, DevBasis B, DevNear NJ, DevNear NT, int nbox,
                                                  const cx<TF>* __restrict__ Gin, const cx<TF>* __restrict__ M,
                                                  const int32_t* __restrict__ anti, int Q, int Qh,
-                                                 const cx<TN>* __restrict__ part, int flags, int W,
-                                                 cx<double>* __restrict__ y, int ldy) {
+                                                 const cx<TN>* __restrict__ partJ, const cx<TN>* __restrict__ partT,
+                                                 int flags, int W, cx<double>* __restrict__ y, int ldy,
+                                                 cx<double>* __restrict__ phi) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_box(blockIdx.x, nbox);
   if (b < 0) return;
@@ -885,14 +1004,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 
   cx<TF>* red = Gs + (size_t)Q * ncol;                     // [ni][6][RC]: A, Bx, By, Bz, Cs, Du
   int32_t* pair = (int32_t*)(red + (size_t)ni * 6 * RC);  // [Qh] antipode of each stored sample
   int32_t* slots = pair + Q;                               // near-field partial-sum slots
-  const double mu0 = 4.0e-7 * 3.14159265358979323846;
-  const int nrow = do_near ? NB.row_ptr[b + 1] - NB.row_ptr[b] : 0;
-  const int nslot = do_near ? nrow + NB.col_ptr[b + 1] - NB.col_ptr[b] : 0;
-  for (int e = threadIdx.x; e < nslot; e += blockDim.x)
-    slots[e] = e < nrow ? NB.prow[NB.row_ptr[b] + e] : NB.pcol[NB.col_blk[NB.col_ptr[b] + e - nrow]];
+  int nslotJ, nslot;
+  near_join_slots(NJ, NT, b, do_near, slots, nslotJ, nslot);
   if (do_far)
     for (int q = Qh + threadIdx.x; q < Q; q += blockDim.x) pair[anti[q]] = q;
-  const int u0 = NB.box_ptr[b], nu = NB.box_ptr[b + 1] - u0;
+  const int u0 = I.uptr[b], nu = I.uptr[b + 1] - u0;
+  const int nJb = NJ.slot_ptr[b + 1] - NJ.slot_ptr[b];  // RWG functions come first in a box
   for (int c0 = 0; c0 < W; c0 += RC) {
     if (c0 > 0) __syncthreads();
     if (do_far) {
@@ -977,51 +1094,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 
       const int ul = e / RC, r = e - ul * RC;
       if (c0 + r >= W) continue;
       const int u = u0 + ul;
-      const int cu = B.perm[u];
-      cx<double> val = mk(0.0, 0.0);
-      if (do_far) {
-        if (cu < B.ne) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const cx<TF>* rv = red + (size_t)(I.uj[2 * u + h] - j0) * 6 * RC + r;
-            const double s = I.us[2 * u + h], d = I.ud[2 * u + h];
-            cx<double> t = mk((double)rv[0].re, (double)rv[0].im);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const double pc = I.upv[6 * (size_t)u + 3 * h + c];
-              t.re -= pc * (double)rv[(1 + c) * RC].re;
-              t.im -= pc * (double)rv[(1 + c) * RC].im;
-            }
-            val.re += mu0 * s * t.re + d * (double)rv[4 * RC].re;
-            val.im += mu0 * s * t.im + d * (double)rv[4 * RC].im;
-          }
-        } else {
-          const cx<TF>* rv = red + (size_t)(I.uj[2 * u] - j0) * 6 * RC + r;
-          val.re += (double)rv[5 * RC].re;
-          val.im += (double)rv[5 * RC].im;
-        }
-      }
-      if (do_near) {
-        const size_t col = (size_t)c0 + r;
-        int k = 0;
-        for (; k + 4 <= nslot; k += 4) {
-          cx<TN> v[4];
-#pragma unroll
-          for (int tt = 0; tt < 4; ++tt) v[tt] = part[((size_t)slots[k + tt] + ul) * W + col];
-#pragma unroll
-          for (int tt = 0; tt < 4; ++tt) {
-            val.re += (double)v[tt].re;
-            val.im += (double)v[tt].im;
-          }
-        }
-        for (; k < nslot; ++k) {
-          const cx<TN> v = part[((size_t)slots[k] + ul) * W + col];
-          val.re += (double)v.re;
-          val.im += (double)v.im;
-        }
-      }
-      if (conj_out) val.im = -val.im;
-      y[(size_t)cu * ldy + c0 + r] = val;
+      auto rv = [&](int h, int o) {
+        const cx<TF> v = red[(size_t)(I.uj[2 * u + h] - j0) * 6 * RC + o * RC + r];
+        return mk((double)v.re, (double)v.im);
+      };
+      receive_unknown<TN>(I, B, u, ul, nJb, r, c0, W, do_far, do_near, conj_out, partJ, partT, slots, nslotJ,
+                          nslot, rv, y, ldy, phi);
     }
   }
 }
@@ -1057,11 +1135,12 @@ size_t mreceive_smem(int maxinc, int maxjoin, int Q) {
 }
 
 template <typename TN>
-__global__ void __launch_bounds__(256) k_mreceive(DevInc I, DevBasis B, DevNear NB, int nbox,
+__global__ void __launch_bounds__(256) k_mreceive(DevInc I, DevBasis B, DevNear NJ, DevNear NT, int nbox,
                                                   const cx<double>* __restrict__ Gin, const cx<double>* __restrict__ M,
                                                   const int32_t* __restrict__ anti, int Q, int Qh, size_t buf,
-                                                  const cx<TN>* __restrict__ part, int flags, int W,
-                                                  cx<double>* __restrict__ y, int ldy) {
+                                                  const cx<TN>* __restrict__ partJ, const cx<TN>* __restrict__ partT,
+                                                  int flags, int W, cx<double>* __restrict__ y, int ldy,
+                                                  cx<double>* __restrict__ phi) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = xcd_box(blockIdx.x, nbox);
   if (b < 0) return;
@@ -1073,11 +1152,8 @@ __global__ void __launch_bounds__(256) k_mreceive(DevInc I, DevBasis B, DevNear 
   cx<double>* red = (cx<double>*)smem;   // [ni][6][MR_COLS]
   int32_t* pairt = (int32_t*)(smem + buf);  // [Q] antipode of each stored sample
   int32_t* slots = pairt + Q;                 // near-field partial-sum slots
-  const double mu0 = 4.0e-7 * 3.14159265358979323846;
-  const int nrow = do_near ? NB.row_ptr[b + 1] - NB.row_ptr[b] : 0;
-  const int nslot = do_near ? nrow + NB.col_ptr[b + 1] - NB.col_ptr[b] : 0;
-  for (int e = threadIdx.x; e < nslot; e += blockDim.x)
-    slots[e] = e < nrow ? NB.prow[NB.row_ptr[b] + e] : NB.pcol[NB.col_blk[NB.col_ptr[b] + e - nrow]];
+  int nslotJ, nslot;
+  near_join_slots(NJ, NT, b, do_near, slots, nslotJ, nslot);
   const bool paired = Qh < Q;
   for (int q = Qh + threadIdx.x; q < Q; q += blockDim.x) pairt[anti[q]] = q;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kq = lane >> 4, jl = lane & 15;
@@ -1167,70 +1243,60 @@ __global__ void __launch_bounds__(256) k_mreceive(DevInc I, DevBasis B, DevNear 
     }
   }
   __syncthreads();
-  const int u0 = NB.box_ptr[b], nu = NB.box_ptr[b + 1] - u0;
+  const int u0 = I.uptr[b], nu = I.uptr[b + 1] - u0;
+  const int nJb = NJ.slot_ptr[b + 1] - NJ.slot_ptr[b];
   for (int e = threadIdx.x; e < nu * MR_COLS; e += blockDim.x) {
     const int ul = e / MR_COLS, r = e - ul * MR_COLS;
     if (c0 + r >= W) continue;
     const int u = u0 + ul;
-    const int cu = B.perm[u];
-    cx<double> val = mk(0.0, 0.0);
-    if (do_far) {
-      if (cu < B.ne) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const cx<double>* rv = red + (size_t)(I.uj[2 * u + h] - j0) * 6 * MR_COLS + r;
-          const double sv = I.us[2 * u + h], d = I.ud[2 * u + h];
-          cx<double> t = rv[0];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double pc = I.upv[6 * (size_t)u + 3 * h + c];
-            t.re -= pc * rv[(1 + c) * MR_COLS].re;
-            t.im -= pc * rv[(1 + c) * MR_COLS].im;
-          }
-          val.re += mu0 * sv * t.re + d * rv[4 * MR_COLS].re;
-          val.im += mu0 * sv * t.im + d * rv[4 * MR_COLS].im;
-        }
-      } else {
-        const cx<double>* rv = red + (size_t)(I.uj[2 * u] - j0) * 6 * MR_COLS + r;
-        val.re += rv[5 * MR_COLS].re;
-        val.im += rv[5 * MR_COLS].im;
-      }
-    }
-    if (do_near) {
-      const size_t col = (size_t)c0 + r;
-      int k = 0;
-      for (; k + 4 <= nslot; k += 4) {
-        cx<TN> v[4];
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) v[tt] = part[((size_t)slots[k + tt] + ul) * W + col];
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-          val.re += (double)v[tt].re;
-          val.im += (double)v[tt].im;
-        }
-      }
-      for (; k < nslot; ++k) {
-        const cx<TN> v = part[((size_t)slots[k] + ul) * W + col];
-        val.re += (double)v.re;
-        val.im += (double)v.im;
-      }
-    }
-    if (conj_out) val.im = -val.im;
-    y[(size_t)cu * ldy + c0 + r] = val;
+    auto rv = [&](int h, int o) { return red[((size_t)(I.uj[2 * u + h] - j0) * 6 + o) * MR_COLS + r]; };
+    receive_unknown<TN>(I, B, u, ul, nJb, r, c0, W, do_far, do_near, conj_out, partJ, partT, slots, nslotJ, nslot,
+                        rv, y, ldy, phi);
   }
 }
 
-// Canonical FP64 x -> box-order x in near-field precision (conjugated for
-// the adjoint).
+// Canonical FP64 x -> the near-field inputs in near-field precision
+// (conjugated for the adjoint): xJ[sJ][W] = x of the RWG function at RWG
+// slot sJ; xT[sT][2W] = (x_A, u) of the triangle at triangle slot sT, with
+// u = div J + w^2 eps0 x_A formed in FP64 from all the RWG functions on it.
 template <typename TN>
-__global__ void k_permute_in(const cx<double>* __restrict__ x, int ldx, const int32_t* __restrict__ perm,
-                             int N, int R, int conjx, cx<TN>* __restrict__ xb) {
+__global__ void k_near_in(const cx<double>* __restrict__ x, int ldx, const int32_t* __restrict__ permJ,
+                          const int32_t* __restrict__ permT, DevTriDiv td, double w2e, int W, int conjx,
+                          cx<TN>* __restrict__ xJ, cx<TN>* __restrict__ xT) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)N * R) return;
-  const int u = (int)(e / R), r = (int)(e - (int64_t)u * R);
-  cx<double> v = x[(size_t)perm[u] * ldx + r];
-  if (conjx) v.im = -v.im;
-  xb[e] = mk((TN)v.re, (TN)v.im);
+  const int64_t nJ = (int64_t)td.ne * W;
+  if (e < nJ) {
+    const int sj = (int)(e / W), r = (int)(e - (int64_t)sj * W);
+    cx<double> v = x[(size_t)permJ[sj] * ldx + r];
+    if (conjx) v.im = -v.im;
+    xJ[e] = mk((TN)v.re, (TN)v.im);
+    return;
+  }
+  const int64_t f = e - nJ;
+  if (f >= (int64_t)td.nt * W) return;
+  const int st = (int)(f / W), r = (int)(f - (int64_t)st * W);
+  const int t = permT[st];
+  cx<double> xa = x[(size_t)(td.ne + t) * ldx + r];
+  if (conjx) xa.im = -xa.im;
+  const cx<double> u = tri_u(td, x, ldx, r, t, xa, w2e, conjx);
+  xT[(size_t)st * 2 * W + r] = mk((TN)xa.re, (TN)xa.im);
+  xT[(size_t)st * 2 * W + W + r] = mk((TN)u.re, (TN)u.im);
+}
+
+// RWG rows += G phi: each RWG function tests the per-triangle potential phi
+// [T][W] of its two triangles with its divergence +-l/A (the JA block
+// G S of the operator; phi already conjugated for the adjoint).  cs holds
+// +-l/(2A) per (edge, half), so the divergence is 2 cs exactly.
+__global__ void k_div_test(const int32_t* __restrict__ tri, const double* __restrict__ cs,
+                           const cx<double>* __restrict__ phi, int ne, int W, cx<double>* __restrict__ y, int ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ne * W) return;
+  const int m = (int)(e / W), r = (int)(e - (int64_t)m * W);
+  const cx<double> p0 = phi[(size_t)tri[2 * m] * W + r], p1 = phi[(size_t)tri[2 * m + 1] * W + r];
+  const double d0 = 2.0 * cs[2 * m], d1 = 2.0 * cs[2 * m + 1];
+  cx<double>& o = y[(size_t)m * ldy + r];
+  o.re += d0 * p0.re + d1 * p1.re;
+  o.im += d0 * p0.im + d1 * p1.im;
 }
 
 // ------------------------------------------------------------- launchers --
@@ -1463,33 +1529,45 @@ hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, vo
 }
 
 template <typename TF, typename TN>
-hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxinc, int maxjoin,
-                          const void* Gin, const void* M, const int32_t* anti, int Q, int Qh, const void* part,
-                          int W, int rc, int flags, void* y, int ldy, hipStream_t st) {
+hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NJ, const DevNear& NT, int nb,
+                          int maxinc, int maxjoin, const void* Gin, const void* M, const int32_t* anti, int Q, int Qh,
+                          const void* partJ, const void* partT, int W, int rc, int flags, void* y, int ldy,
+                          void* phi, hipStream_t st) {
   if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
   if (sizeof(TF) == 8 && W >= MR_COLS && maxinc <= MR_MAXI) {
     const size_t buf = mreceive_buf(maxinc);
     hipLaunchKernelGGL(k_mreceive<TN>, dim3(xcd_grid(nb), (W + MR_COLS - 1) / MR_COLS), dim3(256),
-                       mreceive_smem(maxinc, maxjoin, Q), st, I, B, NB, nb, (const cx<double>*)Gin,
-                       (const cx<double>*)M, anti, Q, Qh, buf, (const cx<TN>*)part, flags, W, (cx<double>*)y, ldy);
+                       mreceive_smem(maxinc, maxjoin, Q), st, I, B, NJ, NT, nb, (const cx<double>*)Gin,
+                       (const cx<double>*)M, anti, Q, Qh, buf, (const cx<TN>*)partJ, (const cx<TN>*)partT, flags,
+                       W, (cx<double>*)y, ldy, (cx<double>*)phi);
     return hipGetLastError();
   }
   const int g = W >= 4 && rc >= 4 ? 4 : (W >= 2 && rc >= 2 ? 2 : 1);
-#define REC(RC_)                                                                                            \
-  hipLaunchKernelGGL((k_receive<TF, TN, RC_>), dim3(xcd_grid(nb)), dim3(256),                               \
-                     receive_smem(maxinc, Q, maxjoin, RC_, sizeof(TF)), st, I, B, NB, nb, (const cx<TF>*)Gin, \
-                     (const cx<TF>*)M, anti, Q, Qh, (const cx<TN>*)part, flags, W, (cx<double>*)y, ldy)
+#define REC(RC_)                                                                                              \
+  hipLaunchKernelGGL((k_receive<TF, TN, RC_>), dim3(xcd_grid(nb)), dim3(256),                                 \
+                     receive_smem(maxinc, Q, maxjoin, RC_, sizeof(TF)), st, I, B, NJ, NT, nb, (const cx<TF>*)Gin, \
+                     (const cx<TF>*)M, anti, Q, Qh, (const cx<TN>*)partJ, (const cx<TN>*)partT, flags, W,       \
+                     (cx<double>*)y, ldy, (cx<double>*)phi)
   if (g == 1) REC(1); else if (g == 2) REC(2); else REC(4);
 #undef REC
   return hipGetLastError();
 }
 
 template <typename TN>
-hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N, int R, int conjx, void* xb,
-                             hipStream_t st) {
-  int64_t n = (int64_t)N * R;
-  hipLaunchKernelGGL(k_permute_in<TN>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                     (const cx<double>*)x, ldx, perm, N, R, conjx, (cx<TN>*)xb);
+hipError_t launch_near_in(const void* x, int ldx, const int32_t* permJ, const int32_t* permT, const DevTriDiv& td,
+                          double w2e, int W, int conjx, void* xJ, void* xT, hipStream_t st) {
+  const int64_t n = ((int64_t)td.ne + td.nt) * W;
+  hipLaunchKernelGGL(k_near_in<TN>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const cx<double>*)x, ldx,
+                     permJ, permT, td, w2e, W, conjx, (cx<TN>*)xJ, (cx<TN>*)xT);
+  return hipGetLastError();
+}
+
+hipError_t launch_div_test(const int32_t* tri, const double* cs, const void* phi, int ne, int W, void* y, int ldy,
+                           hipStream_t st) {
+  const int64_t n = (int64_t)ne * W;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_div_test, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tri, cs,
+                     (const cx<double>*)phi, ne, W, (cx<double>*)y, ldy);
   return hipGetLastError();
 }
 
@@ -1505,13 +1583,13 @@ hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N,
                                                  void* const*, int, int, int, hipStream_t);                    \
   template hipError_t launch_translate<TF>(const DevLevel&, const void*, const void*, void*, int, int,       \
                                            hipStream_t);                                                     \
-  template hipError_t launch_permute_in<TF>(const void*, int, const int32_t*, int, int, int, void*,           \
-                                            hipStream_t);
+  template hipError_t launch_near_in<TF>(const void*, int, const int32_t*, const int32_t*, const DevTriDiv&,  \
+                                         double, int, int, void*, void*, hipStream_t);
 INST_F(float)
 INST_F(double)
-template hipError_t launch_receive<float, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, int, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<double, float>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, int, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<float, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, int, int, int, void*, int, hipStream_t);
-template hipError_t launch_receive<double, double>(const DevInc&, const DevBasis&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, int, int, int, void*, int, hipStream_t);
+template hipError_t launch_receive<float, float>(const DevInc&, const DevBasis&, const DevNear&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, const void*, int, int, int, void*, int, void*, hipStream_t);
+template hipError_t launch_receive<double, float>(const DevInc&, const DevBasis&, const DevNear&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, const void*, int, int, int, void*, int, void*, hipStream_t);
+template hipError_t launch_receive<float, double>(const DevInc&, const DevBasis&, const DevNear&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, const void*, int, int, int, void*, int, void*, hipStream_t);
+template hipError_t launch_receive<double, double>(const DevInc&, const DevBasis&, const DevNear&, const DevNear&, int, int, int, const void*, const void*, const int32_t*, int, int, const void*, const void*, int, int, int, void*, int, void*, hipStream_t);
 
 }  // namespace pie

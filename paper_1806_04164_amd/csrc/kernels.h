@@ -16,10 +16,11 @@ hipError_t launch_diag(const DevGeo& G, const DevBasis& B, double* diag_abs, dou
 // FP64 self blocks of the finest boxes (row-major nb x nb at off[b], box order).
 hipError_t launch_diag_blocks(const DevGeo& G, const DevBasis& B, const int32_t* box_ptr, const int64_t* off,
                               int nbox, void* out, double k, double w2e, hipStream_t st);
-// W right-hand-side columns per pass, register groups of at most rc columns.
+// W columns per pass, register groups of at most rc columns; mfma: FP32
+// entries on the matrix cores.
 template <typename TN>
 hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part, int W, int rc,
-                            hipStream_t st);
+                            bool mfma, hipStream_t st);
 
 // far.hip
 size_t aggregate_smem(int maxinc, int Q, int nsplit, int RC, int tf_bytes);
@@ -51,13 +52,20 @@ hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, vo
 template <typename TF>
 hipError_t launch_translate_levels(const DevLevel* lv, const void* const* S, const void* const* T, void* const* G,
                                    int n, int Q, int R, hipStream_t st);
+// Reception + near join: RWG rows and pulse rows of y (canonical, FP64,
+// leading dimension ldy) and the per-triangle potentials phi [T][W].
 template <typename TF, typename TN>
-hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NB, int nb, int maxinc, int maxjoin,
-                          const void* Gin, const void* M, const int32_t* anti, int Q, int Qh, const void* part,
-                          int W, int rc, int flags, void* y, int ldy, hipStream_t st);
+hipError_t launch_receive(const DevInc& I, const DevBasis& B, const DevNear& NJ, const DevNear& NT, int nb,
+                          int maxinc, int maxjoin, const void* Gin, const void* M, const int32_t* anti, int Q, int Qh,
+                          const void* partJ, const void* partT, int W, int rc, int flags, void* y, int ldy,
+                          void* phi, hipStream_t st);
+// Near-field inputs: RWG slots xJ [E][W] and triangle slots xT [T][2W] (x_A, u).
 template <typename TN>
-hipError_t launch_permute_in(const void* x, int ldx, const int32_t* perm, int N, int R, int conjx, void* xb,
-                             hipStream_t st);
+hipError_t launch_near_in(const void* x, int ldx, const int32_t* permJ, const int32_t* permT, const DevTriDiv& td,
+                          double w2e, int W, int conjx, void* xJ, void* xT, hipStream_t st);
+// y[m] += sum_h 2 cs[m][h] phi[tri[m][h]] for the ne RWG rows.
+hipError_t launch_div_test(const int32_t* tri, const double* cs, const void* phi, int ne, int W, void* y, int ldy,
+                           hipStream_t st);
 
 // aux.hip
 hipError_t launch_rhs(const DevGeo& G, const double* basis_canon_s, const int32_t* tri_canon,

@@ -199,18 +199,28 @@ __device__ cx<double> z_entry(const DevGeo& G, const DevBasis& B, int u, int v, 
   return z;
 }
 
+// Entry of the scalar operator S_qp = <P_q, int P_p g> between the
+// triangles of the pulses at box-order slots u and v.
+__device__ cx<double> s_entry(const DevGeo& G, const DevBasis& B, int u, int v, double k) {
+  Mom m;
+  pair_moments(G, B.tri[2 * u], B.tri[2 * v], k, m);
+  return m.M0;
+}
+
+// One workgroup per stored block (a, b) of a near structure: RWG-RWG
+// entries Z_mn (kind 0) or triangle-triangle entries S_qp (kind 1).
 template <typename TN>
 __global__ void __launch_bounds__(256) k_near_fill(DevGeo G, DevBasis B, DevNear NB, cx<TN>* out,
                                                    double k, double w2e, int32_t blk0) {
   const int blk = blk0 + blockIdx.x;
   const int a = NB.blk_a[blk], b = NB.blk_b[blk];
-  const int u0 = NB.box_ptr[a], na = NB.box_ptr[a + 1] - u0;
-  const int v0 = NB.box_ptr[b], nb = NB.box_ptr[b + 1] - v0;
+  const int ua = NB.ubase[a], na = NB.slot_ptr[a + 1] - NB.slot_ptr[a];
+  const int ub = NB.ubase[b], nb = NB.slot_ptr[b + 1] - NB.slot_ptr[b];
   cx<TN>* o = out + NB.blk_off[blk];
   const int ldz = nb | 1;  // odd row stride of the stored blocks
   for (int e = threadIdx.x; e < na * nb; e += blockDim.x) {
     int i = e / nb, j = e - i * nb;
-    cx<double> z = z_entry(G, B, u0 + i, v0 + j, k, w2e);
+    cx<double> z = NB.kind == 0 ? z_entry(G, B, ua + i, ub + j, k, w2e) : s_entry(G, B, ua + i, ub + j, k);
     o[(size_t)i * ldz + j] = mk((TN)z.re, (TN)z.im);
   }
 }
@@ -399,8 +409,8 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// Batched FP32 near field on the matrix cores (W >= NM_COLS columns in a
-// pass).  Same persistent panel stream as k_near_spmm; for each block of
+// Batched FP32 near field on the matrix cores (passes of at least NM_COLS
+// right-hand sides).  Same persistent panel stream as k_near_spmm; for each block of
 // NM_COLS right-hand-side columns the row part Z x_b and the column part
 // Z^T x_a are complex GEMMs in v_mfma_f32_16x16x4 tiles (four real products
 // per complex one): waves 0 and 1 take the row tiles of the panel, waves 2
@@ -542,11 +552,13 @@ hipError_t launch_diag(const DevGeo& G, const DevBasis& B, double* diag_abs, dou
   return hipGetLastError();
 }
 
-// W columns per pass (x: [N][ldx] box order, part: [slot][W]); rc: widest
-// register group (1, 2 or 4).
+// W columns per pass (x: [slots][ldx] in the structure's slot order, part:
+// [partial slot][W]); rc: widest register group (1, 2 or 4); mfma: FP32
+// entries on the matrix cores (the caller's choice, so that both structures
+// of one pass switch together).
 template <typename TN>
 hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, int ldx, void* part, int W, int rc,
-                            hipStream_t st) {
+                            bool mfma, hipStream_t st) {
   if (NB.ntask == 0) return hipSuccess;
   if (W < 1 || (rc != 1 && rc != 2 && rc != 4)) return hipErrorInvalidValue;
   // persistent grids: as many workgroups as fit on the current device at
@@ -555,7 +567,7 @@ hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, in
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-  if (sizeof(TN) == 4 && W >= NM_COLS) {
+  if (sizeof(TN) == 4 && mfma) {
     static int wgs[kMaxDevices] = {};
     if (wgs[dev] == 0 && (e = resident_workgroups((const void*)k_near_mspmm, dev, wgs[dev])) != hipSuccess) return e;
     hipLaunchKernelGGL(k_near_mspmm, dim3(std::min(NB.ntask, wgs[dev])), dim3(256), 0, st, NB,
@@ -577,8 +589,8 @@ hipError_t launch_near_spmm(const DevNear& NB, const void* Z, const void* xb, in
   return hipGetLastError();
 }
 template hipError_t launch_near_spmm<float>(const DevNear&, const void*, const void*, int, void*, int, int,
-                                            hipStream_t);
+                                            bool, hipStream_t);
 template hipError_t launch_near_spmm<double>(const DevNear&, const void*, const void*, int, void*, int, int,
-                                             hipStream_t);
+                                             bool, hipStream_t);
 
 }  // namespace pie

@@ -50,10 +50,14 @@ struct pie_op {
   int32_t *dCtri = nullptr, *dCfv = nullptr;
   double* dCs = nullptr;
   // near field
-  pie::DevNear NB{};
-  void* dNear = nullptr;
-  int64_t ntask = 0;
-  int64_t near_entries = 0, near_stored = 0, nslots = 0;
+  // near field: RWG-RWG blocks (NJ) and triangle-triangle blocks of the
+  // scalar operator (NT), each stored as its upper triangle
+  pie::DevNear NJ{}, NT{};
+  void *dNearJ = nullptr, *dNearT = nullptr;
+  int64_t near_entries = 0, near_stored_J = 0, near_stored_T = 0, nslots_J = 0, nslots_T = 0;
+  int32_t *dPermJ = nullptr, *dPermT = nullptr;  // RWG / triangle slots -> canonical RWG / triangle
+  int32_t* dBoxPtr = nullptr;                    // [nbL+1] box-order unknown ranges
+  pie::DevTriDiv TD{};                           // divergence sources of the triangles
   // second stream for the near field, forked from and joined to the caller's
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -83,8 +87,9 @@ struct pie_op {
   std::vector<void*> dTl, dFl, dFtl, dPhl;
   // workspace
   std::vector<void*> dS, dG;
-  void* dPart = nullptr;
-  void* dXb = nullptr;
+  void *dPartJ = nullptr, *dPartT = nullptr;  // near partial sums [slot][W], [slot][2W]
+  void *dXbJ = nullptr, *dXbT = nullptr;      // near inputs [E][W], [T][2W] (x_A, u)
+  void* dPhi = nullptr;                       // per-triangle potentials [T][W] (FP64)
   double* dDiagScale = nullptr;  // |Z_uu|^-1/2, canonical order
   // block-diagonal preconditioner (inverses of the finest boxes' FP64 self
   // blocks, box order), built on the first solve that asks for it
@@ -123,6 +128,9 @@ struct pie_op {
 // Widest MVM pass: the far-field workspace holds this many RHS columns;
 // wider batches run in several passes.
 constexpr int kPassMax = 64;
+// Passes of at least this many columns run the batched (matrix-core and
+// sibling-group) kernels.
+constexpr int kBatchCols = 16;
 
 struct pie_graph {
   hipGraph_t graph = nullptr;
@@ -238,6 +246,97 @@ pie_status upload_tables(pie_op* op, const std::vector<double>& khat, const std:
   return PIE_OK;
 }
 
+// One near-field structure (kind 0: RWG-RWG, 1: triangle-triangle) over
+// per-box slot counts cnt: the slots of box b are [sptr[b], sptr[b] + cnt[b])
+// in the structure's slot order and start at box-order unknown ubase[b].
+// Stored blocks (a <= b, both boxes with slots) are grouped by row box and
+// split into row panels of at most one LDS panel (2048 FP32 / 1024 FP64
+// entries), one SpMM work unit each; row_ptr / col_ptr receive the per-box
+// join ranges (host copies).
+pie_status build_near(pie_op* op, const Tree& t, int kind, const std::vector<int32_t>& cnt,
+                      const std::vector<int32_t>& ubase, DevNear& out, int64_t& stored, int64_t& entries,
+                      int64_t& nslots, std::vector<int32_t>& row_ptr, std::vector<int32_t>& col_ptr) {
+  const int nbL = (int)cnt.size();
+  std::vector<int32_t> sptr(nbL + 1, 0);
+  for (int b = 0; b < nbL; ++b) sptr[b + 1] = sptr[b] + cnt[b];
+  const int zcap = op->near_prec == PIE_FP32 ? 2048 : 1024;
+  std::vector<int32_t> ba, bb, prow, col_blk, tpc;
+  row_ptr.assign(nbL + 1, 0);
+  col_ptr.assign(nbL + 1, 0);
+  std::vector<NearTaskDesc> tdesc;
+  std::vector<int64_t> boff;
+  std::vector<std::vector<int32_t>> cols(nbL);
+  int64_t off = 0, slot = 0, ent = 0;
+  for (int a = 0; a < nbL; ++a) {
+    for (int64_t k = t.near_ptr[a]; k < t.near_ptr[a + 1]; ++k) {
+      const int b = (int)t.near_idx[k];
+      const int na = cnt[a], nb = cnt[b];
+      if (b < a || na == 0 || nb == 0) continue;
+      const int id = (int)ba.size();
+      ba.push_back(a);
+      bb.push_back(b);
+      boff.push_back(off);
+      // rows stored with an odd stride nb | 1, so that the SpMM's row-wise
+      // LDS reads (one row per lane) hit distinct banks
+      const int ldz = nb | 1;
+      off += ((int64_t)na * ldz + 3) & ~int64_t(3);  // 4-entry (32-byte FP32) aligned blocks
+      ent += (int64_t)na * nb;
+      prow.push_back((int32_t)slot);
+      slot += na;
+      // one panel when the block fits, else the fewest equal panels (even
+      // row counts for FP32, so that panel starts stay 16-byte aligned)
+      const int cap = std::max(1, std::min(128, zcap / ldz));
+      int rpp = na;
+      if (na > cap) {
+        for (int npn = (na + cap - 1) / cap;; ++npn) {
+          rpp = (na + npn - 1) / npn;
+          if (op->near_prec == PIE_FP32 && (rpp & 1)) ++rpp;
+          if (rpp <= cap) break;
+        }
+      }
+      for (int i0 = 0; i0 < na; i0 += rpp) {
+        const int tid_ = (int)tdesc.size();
+        NearTaskDesc d;
+        d.off = boff[id] + (int64_t)i0 * ldz;
+        d.v0 = sptr[b];
+        d.nb = nb;
+        d.ua = sptr[a] + i0;
+        d.nr = std::min(na, i0 + rpp) - i0;
+        d.prow = prow[id] + i0;
+        if (b != a) {
+          d.pcol = (int32_t)slot;
+          slot += nb;
+          cols[b].push_back(tid_);
+        } else {
+          d.pcol = -1;
+        }
+        tpc.push_back(d.pcol);
+        tdesc.push_back(d);
+      }
+    }
+    row_ptr[a + 1] = (int32_t)ba.size();
+  }
+  for (int b = 0; b < nbL; ++b) {
+    col_ptr[b + 1] = col_ptr[b] + (int32_t)cols[b].size();
+    col_blk.insert(col_blk.end(), cols[b].begin(), cols[b].end());
+  }
+  stored = off;
+  entries = ent;
+  nslots = slot;
+  int32_t *dba, *dbb, *dprow, *dsp, *dub, *drp, *dcp, *dcb, *dtpc;
+  int64_t* dbo;
+  NearTaskDesc* dtd;
+  pie_status s;
+  if ((s = upload(op, &dba, ba)) || (s = upload(op, &dbb, bb)) || (s = upload(op, &dbo, boff)) ||
+      (s = upload(op, &dprow, prow)) || (s = upload(op, &dsp, sptr)) || (s = upload(op, &dub, ubase)) ||
+      (s = upload(op, &drp, row_ptr)) || (s = upload(op, &dcp, col_ptr)) || (s = upload(op, &dcb, col_blk)) ||
+      (s = upload(op, &dtd, tdesc)) || (s = upload(op, &dtpc, tpc)))
+    return s;
+  out = DevNear{kind, (int32_t)ba.size(), dba, dbb, dbo, dprow, (int32_t)tdesc.size(), dtd, dtpc,
+                dsp, dub, drp, dcp, dcb};
+  return PIE_OK;
+}
+
 pie_status build_operator(pie_op* op, hipStream_t st) {
   const Mesh& m = *op->mesh;
   const Tree& t = *op->tree;
@@ -301,96 +400,66 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   if ((s = upload(op, &op->dCfv, cfv))) return s;
   if ((s = upload(op, &op->dCs, cs))) return s;
   DevBasis B{op->dPerm, op->dBtri, op->dBfv, op->dBs, op->dBd, N, ne};
-  // ---------------- near blocks (upper triangle, grouped by row box)
+  // ---------------- near blocks (upper triangle, grouped by row box): the
+  // RWG-RWG blocks over the boxes' RWG slots and the triangle-triangle blocks
+  // of the scalar operator over their triangle slots (each box's RWG
+  // functions come first in box order, then its triangles)
   const Level& fl = t.lev[L];
   const int nbL = (int)fl.nb;
   std::vector<int32_t> box_ptr = narrow32<int32_t>(t.box_ptr);
-  int maxbox = 0;
-  for (int b = 0; b < nbL; ++b) maxbox = std::max(maxbox, box_ptr[b + 1] - box_ptr[b]);
-  if (maxbox > 128) {
-    set_error("a finest box holds more than 128 unknowns; use more levels");
-    return PIE_ERR_UNSUPPORTED;
-  }
-  // blocks (a <= b) grouped by row box; each block split into row panels of
-  // at most one LDS panel (2048 FP32 / 1024 FP64 entries, even row starts so
-  // panels stay 16-byte aligned), one SpMM workgroup per panel
-  const int zcap = op->near_prec == PIE_FP32 ? 2048 : 1024;
-  std::vector<int32_t> ba, bb, prow, row_ptr(nbL + 1, 0), col_ptr(nbL + 1, 0), col_blk;
-  std::vector<int32_t> tpc;
-  std::vector<NearTaskDesc> tdesc;
-  std::vector<int64_t> boff;
-  std::vector<std::vector<int32_t>> cols(nbL);
-  int64_t off = 0, slot = 0, entries = 0;
-  for (int a = 0; a < nbL; ++a) {
-    for (int64_t k = t.near_ptr[a]; k < t.near_ptr[a + 1]; ++k) {
-      int b = (int)t.near_idx[k];
-      if (b < a) continue;
-      int na = box_ptr[a + 1] - box_ptr[a], nb = box_ptr[b + 1] - box_ptr[b];
-      int id = (int)ba.size();
-      ba.push_back(a);
-      bb.push_back(b);
-      boff.push_back(off);
-      // rows stored with an odd stride nb | 1, so that the SpMM's row-wise
-      // LDS reads (one row per lane) hit distinct banks
-      const int ldz = nb | 1;
-      off += ((int64_t)na * ldz + 3) & ~int64_t(3);  // 4-entry (32-byte FP32) aligned blocks
-      entries += (int64_t)na * nb;
-      prow.push_back((int32_t)slot);
-      slot += na;
-      // one panel when the block fits, else the fewest equal panels (even
-      // row counts for FP32, so that panel starts stay 16-byte aligned)
-      const int cap = std::max(1, std::min(128, zcap / ldz));
-      int rpp = na;
-      if (na > cap) {
-        for (int npn = (na + cap - 1) / cap;; ++npn) {
-          rpp = (na + npn - 1) / npn;
-          if (op->near_prec == PIE_FP32 && (rpp & 1)) ++rpp;
-          if (rpp <= cap) break;
-        }
-      }
-      for (int i0 = 0; i0 < na; i0 += rpp) {
-        int tid_ = (int)tdesc.size();
-        NearTaskDesc d;
-        d.off = boff[id] + (int64_t)i0 * ldz;
-        d.v0 = box_ptr[b];
-        d.nb = nb;
-        d.ua = box_ptr[a] + i0;
-        d.nr = std::min(na, i0 + rpp) - i0;
-        d.prow = prow[id] + i0;
-        if (b != a) {
-          d.pcol = (int32_t)slot;
-          slot += nb;
-          cols[b].push_back(tid_);
-        } else {
-          d.pcol = -1;
-        }
-        tpc.push_back(d.pcol);
-        tdesc.push_back(d);
+  std::vector<int32_t> cntJ(nbL, 0), cntT(nbL, 0), permJ, permT;
+  for (int b = 0; b < nbL; ++b)
+    for (int u = box_ptr[b]; u < box_ptr[b + 1]; ++u) {
+      if (perm[u] < ne) {
+        ++cntJ[b];
+        permJ.push_back(perm[u]);
+      } else {
+        ++cntT[b];
+        permT.push_back(perm[u] - ne);
       }
     }
-    row_ptr[a + 1] = (int32_t)ba.size();
-  }
-  for (int b = 0; b < nbL; ++b) {
-    col_ptr[b + 1] = col_ptr[b] + (int32_t)cols[b].size();
-    col_blk.insert(col_blk.end(), cols[b].begin(), cols[b].end());
-  }
-  op->near_stored = off;
-  op->near_entries = entries;
-  op->nslots = slot;
-  op->ntask = (int64_t)tdesc.size();
-  int32_t *dba, *dbb, *dprow, *dbp, *drp, *dcp, *dcb, *dtpc;
-  int64_t* dbo;
-  NearTaskDesc* dtd;
-  if ((s = upload(op, &dba, ba)) || (s = upload(op, &dbb, bb)) || (s = upload(op, &dbo, boff)) ||
-      (s = upload(op, &dprow, prow)) || (s = upload(op, &dbp, box_ptr)) || (s = upload(op, &drp, row_ptr)) ||
-      (s = upload(op, &dcp, col_ptr)) || (s = upload(op, &dcb, col_blk)) || (s = upload(op, &dtd, tdesc)) ||
-      (s = upload(op, &dtpc, tpc)))
+  for (int b = 0; b < nbL; ++b)
+    if (cntJ[b] > 128 || cntT[b] > 128) {
+      set_error("a finest box holds more than 128 RWG functions or 128 triangles; use more levels");
+      return PIE_ERR_UNSUPPORTED;
+    }
+  if ((s = upload(op, &op->dPermJ, permJ)) || (s = upload(op, &op->dPermT, permT)) ||
+      (s = upload(op, &op->dBoxPtr, box_ptr)))
     return s;
-  op->NB = DevNear{(int32_t)ba.size(), dba, dbb, dbo, dprow, (int32_t)tdesc.size(), dtd, dtpc,
-                   dbp, drp, dcp, dcb};
+  std::vector<int32_t> row_ptr_J, col_ptr_J, row_ptr_T, col_ptr_T;
+  int64_t entJ = 0, entT = 0;
+  {
+    std::vector<int32_t> ubJ(nbL), ubT(nbL);
+    for (int b = 0; b < nbL; ++b) {
+      ubJ[b] = box_ptr[b];
+      ubT[b] = box_ptr[b] + cntJ[b];
+    }
+    if ((s = build_near(op, t, 0, cntJ, ubJ, op->NJ, op->near_stored_J, entJ, op->nslots_J, row_ptr_J, col_ptr_J)) ||
+        (s = build_near(op, t, 1, cntT, ubT, op->NT, op->near_stored_T, entT, op->nslots_T, row_ptr_T, col_ptr_T)))
+      return s;
+  }
+  op->near_entries = entJ + entT;
+  // divergence sources of every triangle (canonical): the RWG functions on
+  // its edges with +-l/A (the same value as the box-order divergences)
+  {
+    std::vector<int32_t> te(3 * (size_t)nt, -1);
+    std::vector<double> td(3 * (size_t)nt, 0.0);
+    std::vector<int> fill(nt, 0);
+    for (int e = 0; e < ne; ++e)
+      for (int h = 0; h < 2; ++h) {
+        const int tr = m.etri[2 * e + h];
+        const int k = fill[tr]++;
+        te[3 * (size_t)tr + k] = e;
+        td[3 * (size_t)tr + k] = (h == 0 ? 1.0 : -1.0) * m.elen[e] / m.area[tr];
+      }
+    int32_t* dte;
+    double* dtd;
+    if ((s = upload(op, &dte, te)) || (s = upload(op, &dtd, td))) return s;
+    op->TD = DevTriDiv{dte, dtd, (int32_t)nt, (int32_t)ne};
+  }
   // ---------------- incidences
   std::vector<int32_t> iptr(nbL + 1, 0), itri, irwg, ifv, ipulse, uslot(2 * (size_t)N, -1);
-  std::vector<double> irs, ird;
+  std::vector<double> irs;
   int maxinc = 0;
   for (int b = 0; b < nbL; ++b) {
     std::map<int, int> local;  // triangle -> incidence index
@@ -403,7 +472,6 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
         irwg.push_back(-1);
         ifv.push_back(0);
         irs.push_back(0.0);
-        ird.push_back(0.0);
       }
       ipulse.push_back(-1);
       local[tr] = j;
@@ -417,7 +485,6 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
           while (irwg[3 * j + k] >= 0) ++k;  // at most three edges per triangle
           irwg[3 * j + k] = u;
           irs[3 * j + k] = bs[2 * u + h];
-          ird[3 * j + k] = bd[2 * u + h];
           ifv[3 * j + k] = bfv[2 * u + h];
           uslot[2 * u + h] = 4 * j + k;
         }
@@ -442,7 +509,7 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     std::vector<double> ipw(28 * ni), ipv(9 * ni, 0.0);
     std::vector<int32_t> ixc(4 * ni, -1);
     std::vector<int32_t> uj(2 * (size_t)N, 0);
-    std::vector<double> us(2 * (size_t)N, 0.0), ud(2 * (size_t)N, 0.0), upv(6 * (size_t)N, 0.0);
+    std::vector<double> us(2 * (size_t)N, 0.0), upv(6 * (size_t)N, 0.0);
     for (int b = 0; b < nbL; ++b) {
       const double C[3] = {centre(b, 0), centre(b, 1), centre(b, 2)};
       for (int j = iptr[b]; j < iptr[b + 1]; ++j) {
@@ -454,7 +521,7 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
         for (int k = 0; k < 3; ++k) {
           const int u = irwg[3 * j + k];
           if (u < 0) {
-            irs[3 * j + k] = ird[3 * j + k] = 0.0;
+            irs[3 * j + k] = 0.0;
             continue;
           }
           ixc[4 * (size_t)j + k] = perm[u];
@@ -469,23 +536,22 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
           uj[2 * u + h] = j;
           if (k == 3) continue;
           us[2 * u + h] = irs[3 * j + k];
-          ud[2 * u + h] = ird[3 * j + k];
           for (int c = 0; c < 3; ++c) upv[6 * (size_t)u + 3 * h + c] = m.V[3 * (size_t)ifv[3 * j + k] + c] - C[c];
         }
     }
     int32_t *dip, *dxc, *duj;
-    double *dpw, *drs, *drd, *dpv, *dus, *dud, *dupv;
+    double *dpw, *drs, *dpv, *dus, *dupv;
     if ((s = upload(op, &dip, iptr)) || (s = upload(op, &dpw, ipw)) || (s = upload(op, &dxc, ixc)) ||
-        (s = upload(op, &drs, irs)) || (s = upload(op, &drd, ird)) || (s = upload(op, &dpv, ipv)) ||
-        (s = upload(op, &duj, uj)) || (s = upload(op, &dus, us)) || (s = upload(op, &dud, ud)) ||
-        (s = upload(op, &dupv, upv)))
+        (s = upload(op, &drs, irs)) || (s = upload(op, &dpv, ipv)) || (s = upload(op, &duj, uj)) ||
+        (s = upload(op, &dus, us)) || (s = upload(op, &dupv, upv)))
       return s;
-    op->I = DevInc{dip, dpw, dxc, drs, drd, dpv, duj, dus, dud, dupv};
+    op->I = DevInc{dip, dpw, dxc, drs, dpv, duj, dus, dupv, op->dBoxPtr, op->TD};
   }
   // longest near-field join list of a finest box (partial-sum slots staged in LDS by the reception)
   op->maxjoin = 0;
   for (int b = 0; b < nbL; ++b)
-    op->maxjoin = std::max(op->maxjoin, (row_ptr[b + 1] - row_ptr[b]) + (col_ptr[b + 1] - col_ptr[b]));
+    op->maxjoin = std::max(op->maxjoin, (row_ptr_J[b + 1] - row_ptr_J[b]) + (col_ptr_J[b + 1] - col_ptr_J[b]) +
+                                            (row_ptr_T[b + 1] - row_ptr_T[b]) + (col_ptr_T[b + 1] - col_ptr_T[b]));
   // ---------------- levels
   op->lv.assign(L + 1, DevLevel{});
   op->s_l.assign(L + 1, 0.0);
@@ -722,11 +788,17 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     op->dS[l] = a;
     op->dG[l] = b;
   }
-  unsigned char *part, *xb;
-  if ((s = dalloc(op, &part, (size_t)op->nslots * op->pw * cxn)) || (s = dalloc(op, &xb, (size_t)N * op->pw * cxn)))
+  unsigned char *partJ, *partT, *xbJ, *xbT, *phi;
+  if ((s = dalloc(op, &partJ, (size_t)op->nslots_J * op->pw * cxn)) ||
+      (s = dalloc(op, &partT, (size_t)op->nslots_T * 2 * op->pw * cxn)) ||
+      (s = dalloc(op, &xbJ, (size_t)ne * op->pw * cxn)) || (s = dalloc(op, &xbT, (size_t)nt * 2 * op->pw * cxn)) ||
+      (s = dalloc(op, &phi, (size_t)nt * op->pw * 16)))
     return s;
-  op->dPart = part;
-  op->dXb = xb;
+  op->dPartJ = partJ;
+  op->dPartT = partT;
+  op->dXbJ = xbJ;
+  op->dXbT = xbT;
+  op->dPhi = phi;
   if ((s = dalloc(op, &op->dKhR, 3 * (size_t)op->max_rhs)) || (s = dalloc(op, &op->dPolR, 3 * (size_t)op->max_rhs)) ||
       (s = dalloc(op, &op->dAmpR, 2 * (size_t)op->max_rhs)))
     return s;
@@ -770,13 +842,18 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     if (em != hipSuccess) return hip_fail(em, "moments launch");
   }
   // ---------------- near-field fill and diagonal (FP64 arithmetic)
-  unsigned char* nz;
-  if ((s = dalloc(op, &nz, (size_t)op->near_stored * cxn))) return s;
-  op->dNear = nz;
-  HIPCHK(hipMemset(nz, 0, (size_t)op->near_stored * cxn), "near clear");  // row padding and block tails
-  hipError_t e = op->near_prec == PIE_FP32 ? launch_near_fill<float>(G, B, op->NB, nz, op->k, op->w2e, st)
-                                           : launch_near_fill<double>(G, B, op->NB, nz, op->k, op->w2e, st);
-  if (e != hipSuccess) return hip_fail(e, "near fill launch");
+  hipError_t e;
+  for (int kind = 0; kind < 2; ++kind) {
+    const int64_t stored = kind == 0 ? op->near_stored_J : op->near_stored_T;
+    const DevNear& NS = kind == 0 ? op->NJ : op->NT;
+    unsigned char* nz;
+    if ((s = dalloc(op, &nz, (size_t)stored * cxn))) return s;
+    (kind == 0 ? op->dNearJ : op->dNearT) = nz;
+    HIPCHK(hipMemset(nz, 0, (size_t)stored * cxn), "near clear");  // row padding and block tails
+    e = op->near_prec == PIE_FP32 ? launch_near_fill<float>(G, B, NS, nz, op->k, op->w2e, st)
+                                  : launch_near_fill<double>(G, B, NS, nz, op->k, op->w2e, st);
+    if (e != hipSuccess) return hip_fail(e, "near fill launch");
+  }
   double* diag_box;
   if ((s = dalloc(op, &diag_box, N)) || (s = dalloc(op, &op->dDiagScale, N))) return s;
   if ((e = launch_diag(G, B, diag_box, op->k, op->w2e, st)) != hipSuccess) return hip_fail(e, "diag launch");
@@ -834,11 +911,16 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
       HIPCHK(hipStreamWaitEvent(sn, op->ev_fork, 0), "fork");
     }
     if ((e = stage(op, PIE_STAGE_PERMUTE, sn, [&] {
-           return launch_permute_in<TN>(x, ld, op->dPerm, op->N, R, adj, op->dXb, sn);
+           return launch_near_in<TN>(x, ld, op->dPermJ, op->dPermT, op->TD, op->w2e, R, adj, op->dXbJ, op->dXbT, sn);
          })) != hipSuccess)
-      return hip_fail(e, "permute");
+      return hip_fail(e, "near input");
+    // the scalar operator's blocks act on both x_A and u (2R columns); both
+    // structures take the matrix-core path for batched passes
+    const bool mf = R >= kBatchCols;
     if ((e = stage(op, PIE_STAGE_NEAR, sn, [&] {
-           return launch_near_spmm<TN>(op->NB, op->dNear, op->dXb, R, op->dPart, R, rcap, sn);
+           hipError_t e1 = launch_near_spmm<TN>(op->NJ, op->dNearJ, op->dXbJ, R, op->dPartJ, R, rcap, mf, sn);
+           if (e1 != hipSuccess) return e1;
+           return launch_near_spmm<TN>(op->NT, op->dNearT, op->dXbT, 2 * R, op->dPartT, 2 * R, rcap, mf, sn);
          })) != hipSuccess)
       return hip_fail(e, "near spmm");
     if (fork) HIPCHK(hipEventRecord(op->ev_join, sn), "join");
@@ -947,8 +1029,11 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
   int rflags = (near ? 1 : 0) | (far ? 2 : 0) | (adj ? 4 : 0);
   if (fork) HIPCHK(hipStreamWaitEvent(st, op->ev_join, 0), "join");
   if ((e = stage(op, PIE_STAGE_RECEIVE, st, [&] {
-         return launch_receive<TF, TN>(op->I, B, op->NB, op->lv[L].nb, op->maxinc, op->maxjoin, op->dG[L],
-                                       op->dM, op->dAnti, Q, op->Qh, op->dPart, R, rcap, rflags, y, ld, st);
+         hipError_t e1 = launch_receive<TF, TN>(op->I, B, op->NJ, op->NT, op->lv[L].nb, op->maxinc, op->maxjoin,
+                                                op->dG[L], op->dM, op->dAnti, Q, op->Qh, op->dPartJ, op->dPartT, R,
+                                                rcap, rflags, y, ld, op->dPhi, st);
+         if (e1 != hipSuccess) return e1;
+         return launch_div_test(op->dCtri, op->dCs, op->dPhi, op->ne, R, y, ld, st);
        })) != hipSuccess)
     return hip_fail(e, "receive");
   return PIE_OK;
@@ -1150,7 +1235,7 @@ pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq
   op->far_prec = opt->far_prec;
   const bool f32 = opt->far_prec == PIE_FP32;
   op->tau = opt->tau > 0 ? opt->tau : (f32 ? 4 : 7);
-  op->xs = opt->x > 0.0 ? opt->x : (f32 ? 0.15 : 0.05);
+  op->xs = opt->x > 0.0 ? opt->x : (f32 ? 0.15 : 0.08);
   op->nth = opt->n_theta > 0 ? opt->n_theta : op->tau + 1;
   op->nph = opt->n_phi > 0 ? opt->n_phi : 2 * op->tau + 2;
   op->Q = op->nth * op->nph;
@@ -1209,7 +1294,7 @@ pie_status pie_operator_info(const pie_op* op, int32_t what, int64_t* value) {
     case PIE_OI_N: *value = op->N; break;
     case PIE_OI_Q: *value = op->Q; break;
     case PIE_OI_TAU: *value = op->tau; break;
-    case PIE_OI_NEAR_BLOCKS: *value = op->NB.nblk; break;
+    case PIE_OI_NEAR_BLOCKS: *value = op->NJ.nblk + op->NT.nblk; break;
     case PIE_OI_NEAR_ENTRIES: *value = op->near_entries; break;
     case PIE_OI_NEAR_BYTES: *value = op->near_entries * (op->near_prec == PIE_FP32 ? 8 : 16); break;
     case PIE_OI_NBOX_FINEST: *value = op->lv[op->L].nb; break;
@@ -1578,7 +1663,7 @@ pie_status build_prec(pie_op* op) {
   pie_status s;
   if ((s = dalloc(op, &blocks, (size_t)off[nbox])) || (s = dalloc(op, &doff, (size_t)nbox + 1))) return s;
   HIPCHK(hipMemcpy(doff, off.data(), (nbox + 1) * sizeof(int64_t), hipMemcpyHostToDevice), "prec offsets");
-  hipError_t e = launch_diag_blocks(geo(op), basis(op), op->NB.box_ptr, doff, nbox, blocks, op->k, op->w2e, nullptr);
+  hipError_t e = launch_diag_blocks(geo(op), basis(op), op->dBoxPtr, doff, nbox, blocks, op->k, op->w2e, nullptr);
   if (e != hipSuccess) return hip_fail(e, "self blocks");
   HIPCHK(hipDeviceSynchronize(), "self blocks");
   std::vector<std::complex<double>> h((size_t)off[nbox]);
@@ -1705,7 +1790,7 @@ pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xh
     for (; j < m && total < o.maxit; ++j) {
       ++total;
       cx<double>* vj = V + (size_t)j * NR;
-      e = prec ? launch_block_prec(vj, op->dDiagScale, op->dPrec, op->dPrecOff, op->NB.box_ptr, op->dPerm, nbox, R,
+      e = prec ? launch_block_prec(vj, op->dDiagScale, op->dPrec, op->dPrecOff, op->dBoxPtr, op->dPerm, nbox, R,
                                    tmp, st)
                : launch_scale_rows(vj, op->dDiagScale, N, R, tmp, st);
       if (e != hipSuccess) return hip_fail(e, "scale");
@@ -1783,7 +1868,7 @@ pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xh
         // tmp = V y; w = Minv D^-1 tmp; xhat += D^-1 w
         HIPCHK(hipMemsetAsync(tmp, 0, NR * 16, st), "zero");
         if ((e = launch_update(tmp, V, NR, kmax, dh, N, R, st)) != hipSuccess) return hip_fail(e, "update");
-        if ((e = launch_block_prec(tmp, op->dDiagScale, op->dPrec, op->dPrecOff, op->NB.box_ptr, op->dPerm, nbox, R,
+        if ((e = launch_block_prec(tmp, op->dDiagScale, op->dPrec, op->dPrecOff, op->dBoxPtr, op->dPerm, nbox, R,
                                    w, st)) != hipSuccess)
           return hip_fail(e, "preconditioner");
         if ((e = launch_add_scaled(xhat, w, op->dDiagScale, N, R, st)) != hipSuccess) return hip_fail(e, "update");
@@ -1900,7 +1985,7 @@ extern "C" pie_status pie_precond_apply(pie_op* op, const void* x, void* y, int6
   if (s) return s;
   if (!op->dPrec && (s = build_prec(op))) return s;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_block_prec(x, nullptr, op->dPrec, op->dPrecOff, op->NB.box_ptr, op->dPerm,
+  hipError_t e = launch_block_prec(x, nullptr, op->dPrec, op->dPrecOff, op->dBoxPtr, op->dPerm,
                                    (int)op->tree->lev[op->L].nb, (int)R, y, st);
   if (e != hipSuccess) return hip_fail(e, "preconditioner");
   return PIE_OK;

@@ -7,9 +7,9 @@ Tolerances and where they come from:
   round-off by about (2 tau + 1)!!/(2x)^tau = 1.2e5, so FP64 differences of
   order 1e-16 * 1.2e5 ~ 1e-11 are expected.
 * far field, FP64, tau=6, x=0.07: amplification 1.8e10, so 1e-5.
-* far field, FP64, tau=7, x=0.05 (the FP64 default): amplification bound
-  15!!/0.1^7 = 2e13, i.e. at most ~2e-3 from FP64 rounding; held to that
-  bound (the realised difference is printed).
+* far field, FP64, tau=7, x=0.08 (the FP64 default): amplification bound
+  15!!/0.16^7 = 7.6e11, i.e. at most ~8e-5 from FP64 rounding; the realised
+  nonlinearity of the MVM is about 3e-6, so 1e-4.
 * far field, FP32, tau=4, x=0.15: amplification about 1e5 times FP32
   rounding 6e-8 gives ~6e-3, and the charge of an RWG current nearly cancels
   (the divergence pattern is a dipole), which costs another factor of a few
@@ -90,7 +90,7 @@ def test_near_field(c1, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tau,xs,tol", [(PIE_FP64, 4, 0.15, 1e-9), (PIE_FP64, 6, 0.07, 1e-5),
-                                              (PIE_FP64, 7, 0.05, 2e-3),
+                                              (PIE_FP64, 7, 0.08, 1e-4),
                                              (PIE_FP32, 4, 0.15, 3e-2)])
 def test_far_field_single_level(c1, prec, tau, xs, tol):
     op = _op(c1, far=prec, tau=tau, x=xs)
@@ -177,7 +177,7 @@ def test_batched_aggregation(c1):
     column equals itself bit for bit in any pass of 16 or more columns,
     agrees with its single-column MVM (vector aggregation, other summation
     order) to FP64 rounding carried through the translation (which amplifies
-    it: at tau = 7, x = 0.05 the MVM is linear only to ~1e-8, so 1e-7), and
+    it: at tau = 7, x = 0.08 the MVM is linear only to ~3e-6, so 1e-5), and
     matches the oracle's MLFMA far field."""
     R = 20
     op = _op(c1, max_rhs=R)
@@ -191,12 +191,12 @@ def test_batched_aggregation(c1):
             y = host(mv(dev(X[:, r:r + 1].copy())))[:, 0]
             d = np.linalg.norm(Y[:, r] - y) / np.linalg.norm(y)
             print("batched vs single column", adj, r, d, flush=True)
-            assert d < 1e-7
-    M = mlfma.MLFMA(c1["prob"], 3, mlfma.Params(tau=7, x=0.05))
+            assert d < 1e-5
+    M = mlfma.MLFMA(c1["prob"], 3, mlfma.Params(tau=7, x=0.08))
     errs = block_errors(lambda v: host(op.matvec_far(dev(np.repeat(v[:, None], R, axis=1))))[:, 11],
                         M.far, c1["x"], c1["E"])
     print("batched far vs oracle", errs, flush=True)
-    assert max(errs.values()) < 2e-3
+    assert max(errs.values()) < 1e-4
 
 
 def test_fp32_operator_batched(c1):

@@ -126,8 +126,22 @@ pie_status pie_tree_query(const pie_tree* t, int32_t what, int32_t level,
  * reproduced; here s_l = min(1, k d_l / x) per level, so that the scaled box
  * size k d_l / s_l equals x wherever s < 1, and (tau, x) default per far
  * precision to values chosen by measured error against the dense matrix
- * (sampled rows, 5 to 8 levels):
- *   far FP64: tau = 7, x = 0.05 (Q = 128);  far FP32: tau = 4, x = 0.15.
+ * (sampled rows, 4 to 8 levels) and by the rounding that the sampled
+ * translation amplifies by about (2 tau + 1)!!/(2 x)^tau:
+ *   far FP64: tau = 7 (Q = 128), x = 0.08 for trees of up to 5 levels,
+ *             0.07 for 6 and 0.06 for 7 or more (deeper trees accumulate
+ *             more of the inter-level rescaling error, which grows as x^2);
+ *   far FP32: tau = 4, x = 0.15.
+ * Near/far split (Section 3 does not state it): Z^JA = G S, Z^AJ = S G^T and
+ * Z^AA = w^2 eps0 S share the scalar operator S_qp = <P_q, int P_p g> (G: the
+ * RWG divergence per triangle).  S is applied per triangle -- each triangle's
+ * sources sigma = x_A and u = div J + w^2 eps0 x_A radiate and are received at
+ * the finest box of its centroid, and a triangle pair is near when those
+ * boxes are -- and the vector part mu0 <f_m, int f_n g> per RWG function (the
+ * box of its edge midpoint), so the approximation keeps that identity:
+ * divergence-free currents have no scalar source and the JA block keeps the
+ * charge null vector of the dense matrix, which keeps low-frequency solves
+ * as accurate as the operator.
  * k-space samples: n_theta Gauss-Legendre points in cos(theta) (default
  * tau+1) times n_phi uniform phi (default 2 tau + 2).
  * near_prec: storage and arithmetic of the near-field SpMM.
@@ -144,8 +158,16 @@ typedef struct pie_options {
   int32_t max_rhs;   /* calls take up to this many RHS (>= 1); the far-
                         field workspace holds min(max_rhs, 64) columns,
                         wider calls run in passes of 64 */
-  int32_t reserved;  /* 0                                              */
+  int32_t flags;     /* 0, or PIE_OPT_* bits below (the former reserved
+                        field; version 1 callers pass 0)              */
 } pie_options;
+
+/* pie_options.flags: run the FP64 inter-level shifts on the matrix cores at
+ * every level.  By default they run there only where a level has enough
+ * (parent group, 32-sample block) work items to fill the device; this
+ * option exists so that small trees can pin those kernels against the
+ * oracle.  The result differs from the default only by FP64 rounding. */
+#define PIE_OPT_MATRIX_SHIFTS 1
 
 /* Fills *o with defaults (FP64 near and far, max_rhs 1). */
 void pie_options_default(pie_options* o);

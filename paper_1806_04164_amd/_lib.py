@@ -26,6 +26,7 @@ PIE_ERR_HIP = -6
 PIE_ERR_UNSUPPORTED = -7
 PIE_WARN_NOT_CONVERGED = 1
 PIE_FP32 = 32
+PIE_OPT_MATRIX_SHIFTS = 1
 PIE_FP64 = 64
 PIE_NEAR_SERIAL = 0
 PIE_NEAR_FORK_START = 1
@@ -54,7 +55,7 @@ class pie_options(ctypes.Structure):
     _fields_ = [("version", ctypes.c_int32), ("near_prec", ctypes.c_int32),
                 ("far_prec", ctypes.c_int32), ("tau", ctypes.c_int32), ("x", ctypes.c_double),
                 ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32),
-                ("max_rhs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("max_rhs", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class pie_schedule(ctypes.Structure):

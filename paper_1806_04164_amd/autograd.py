@@ -8,26 +8,51 @@ convention for complex inputs (dL/dRe z + i dL/dIm z for a real loss L).
 """
 from __future__ import annotations
 
+import warnings
+
 import numpy as np
 import torch
 
 
+def _check(info, what, on_fail):
+    if info["converged"]:
+        return
+    msg = (f"{what} solve stopped at relative residual {info['rel_residual']:.3e} after "
+           f"{info['iterations']} iterations (tolerance not met)")
+    if on_fail == "warn":
+        warnings.warn(msg, RuntimeWarning, stacklevel=3)
+    else:
+        raise RuntimeError(msg)
+
+
 class PieSolve(torch.autograd.Function):
-    """x = Z^-1 b with GMRES on the operator; backward solves Z^H g = grad_x."""
+    """x = Z^-1 b with GMRES on the operator; backward solves Z^H g = grad_x.
+    A forward or adjoint solve that misses its tolerance raises RuntimeError
+    (on_fail="raise", the default) or warns (on_fail="warn"); the solve
+    reports of the last call are kept in PieSolve.last_info."""
+
+    last_info = {}
 
     @staticmethod
     def forward(ctx, b, op, solve_kw):
-        x, info = op.solve(b.contiguous(), **solve_kw)
+        kw = dict(solve_kw)
+        on_fail = kw.pop("on_fail", "raise")
+        x, info = op.solve(b.contiguous(), **kw)
+        PieSolve.last_info = {"forward": info}
+        _check(info, "forward", on_fail)
         ctx.op = op
-        ctx.kw = dict(solve_kw)
-        ctx.info = info
+        ctx.kw = kw
+        ctx.on_fail = on_fail
         return x
 
     @staticmethod
     def backward(ctx, gx):
         kw = dict(ctx.kw)
         kw.pop("adjoint", None)
-        g, _ = ctx.op.solve(gx.contiguous(), adjoint=True, **kw)
+        kw.pop("x", None)  # the adjoint solve gets a fresh, zero-initialised output
+        g, info = ctx.op.solve(gx.contiguous(), adjoint=True, **kw)
+        PieSolve.last_info["adjoint"] = info
+        _check(info, "adjoint", ctx.on_fail)
         return g, None, None
 
 

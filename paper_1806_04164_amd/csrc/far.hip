@@ -1346,13 +1346,14 @@ size_t shift_smem(int Q, int tf_bytes) {
 
 template <typename TF>
 hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* Sc, void* Sp, const void* Ft,
-                           const void* ph, int Q, int R, hipStream_t st) {
+                           const void* ph, int Q, int R, bool force_mfma, hipStream_t st) {
   static_assert(SHIFT_GROUP * 5 <= SHIFT_LANES, "shift group exceeds its lanes");
   // matrix cores when the level has enough (group, row block) items to fill
   // the device, counting 16 columns for batched passes (so that the choice
   // is the same for every batched pass width); the vector kernel (more,
   // shorter work items) otherwise
-  if (sizeof(TF) == 8 && Lp.nug * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS) {
+  if (sizeof(TF) == 8 &&
+      (force_mfma || Lp.nug * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS)) {
     const int ntile = (Q + MS_ROWS - 1) / MS_ROWS, nchunk = (R + MS_RCH - 1) / MS_RCH;
     const unsigned grid = 8u * (unsigned)(((Lp.nug + 7) / 8) * ntile * nchunk);
     const size_t sm = mshift_smem(Q) + MS_ROWS * MS_COLS * sizeof(double) +
@@ -1370,9 +1371,9 @@ hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* S
 
 template <typename TF>
 hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const void* F, const void* ph, int Q,
-                             int R, hipStream_t st) {
+                             int R, bool force_mfma, hipStream_t st) {
   const int ng = (Lc.nb + SHIFT_GROUP - 1) / SHIFT_GROUP;
-  if (sizeof(TF) == 8 && ng * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS) {
+  if (sizeof(TF) == 8 && (force_mfma || ng * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS)) {
     const int ntile = (Q + MS_ROWS - 1) / MS_ROWS, nchunk = (R + MS_RCH - 1) / MS_RCH;
     const unsigned grid = 8u * (unsigned)(((ng + 7) / 8) * ntile * nchunk);
     const size_t sm = mshift_smem(Q) + MS_ROWS * MS_COLS * sizeof(double) + 8 * (size_t)Q * sizeof(cx<double>);
@@ -1576,9 +1577,9 @@ hipError_t launch_div_test(const int32_t* tri, const double* cs, const void* phi
   template hipError_t launch_aggregate<TF>(const DevInc&, int, int, const void*, int, int, int, const void*,   \
                                            const int32_t*, int, int, double, int, int, void*, hipStream_t); \
   template hipError_t launch_shift_up<TF>(const DevLevel&, const DevLevel&, const void*, void*, const void*,  \
-                                          const void*, int, int, hipStream_t);                               \
+                                          const void*, int, int, bool, hipStream_t);                         \
   template hipError_t launch_shift_down<TF>(const DevLevel&, const void*, void*, const void*, const void*,   \
-                                            int, int, hipStream_t);                                          \
+                                            int, int, bool, hipStream_t);                                    \
   template hipError_t launch_translate_levels<TF>(const DevLevel*, const void* const*, const void* const*,       \
                                                  void* const*, int, int, int, hipStream_t);                    \
   template hipError_t launch_translate<TF>(const DevLevel&, const void*, const void*, void*, int, int,       \

@@ -38,12 +38,13 @@ hipError_t launch_aggregate(const DevInc& I, int nb, int maxinc, const void* x, 
                             void* S, hipStream_t st);
 // Filter tables (Ft for the upward, F for the downward shift) carry SQT
 // trailing zeros.
+// force_mfma: FP64 shifts on the matrix cores whatever the level's size.
 template <typename TF>
 hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* Sc, void* Sp, const void* Ft,
-                           const void* ph, int Q, int R, hipStream_t st);
+                           const void* ph, int Q, int R, bool force_mfma, hipStream_t st);
 template <typename TF>
 hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const void* F, const void* ph, int Q,
-                             int R, hipStream_t st);
+                             int R, bool force_mfma, hipStream_t st);
 // T: translation values [TRANSLATE_OFFSETS][Q].
 template <typename TF>
 hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, void* Gout, int Q, int R,

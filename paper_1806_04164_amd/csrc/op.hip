@@ -6,6 +6,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -73,6 +74,7 @@ struct pie_op {
   int sched_near = PIE_NEAR_FORK_START;  // where the near field forks off the far chain
   int sched_il = 1;                      // finest translation on the third stream
   int sched_chunk = 4;                   // widest RHS chunk (1, 2 or 4; at most rc)
+  bool force_ms = false;                 // PIE_OPT_MATRIX_SHIFTS
   // incidences
   pie::DevInc I{};
   int64_t ninc = 0;
@@ -983,7 +985,7 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
     for (int l = L - 1; l >= 3; --l) {
       if ((e = stage(op, PIE_STAGE_SHIFT_UP, st, [&] {
              return launch_shift_up<TF>(op->lv[l], op->lv[l + 1], op->dS[l + 1], op->dS[l], op->dFtl[l],
-                                        op->dPhl[l], Q, R, st);
+                                        op->dPhl[l], Q, R, op->force_ms, st);
            })) != hipSuccess)
         return hip_fail(e, "shift up");
       if (l == L - 1 && fork2 && op->sched_il == 2) {
@@ -1021,7 +1023,7 @@ pie_status mvm_chunk(pie_op* op, const void* x, void* y, int ld, int R, int flag
       if (perlev) HIPCHK(hipStreamWaitEvent(st, op->ev_g[l], 0), "join");
       if ((e = stage(op, PIE_STAGE_SHIFT_DOWN, st, [&] {
              return launch_shift_down<TF>(op->lv[l], op->dG[l - 1], op->dG[l], op->dFl[l - 1], op->dPhl[l - 1],
-                                          Q, R, st);
+                                          Q, R, op->force_ms, st);
            })) != hipSuccess)
         return hip_fail(e, "shift down");
     }
@@ -1216,6 +1218,10 @@ pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq
     pie::set_error("precision must be PIE_FP32 or PIE_FP64");
     return PIE_ERR_ARG;
   }
+  if (opt->flags & ~PIE_OPT_MATRIX_SHIFTS) {
+    pie::set_error("unknown pie_options.flags bits");
+    return PIE_ERR_ARG;
+  }
   if (opt->max_rhs < 1 || opt->max_rhs > 4096) {
     pie::set_error("max_rhs must be in [1, 4096]");
     return PIE_ERR_ARG;
@@ -1235,11 +1241,17 @@ pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq
   op->far_prec = opt->far_prec;
   const bool f32 = opt->far_prec == PIE_FP32;
   op->tau = opt->tau > 0 ? opt->tau : (f32 ? 4 : 7);
-  op->xs = opt->x > 0.0 ? opt->x : (f32 ? 0.15 : 0.08);
+  // FP64 far field: x = 0.08 keeps the translation's rounding nonlinearity
+  // near 4e-6; deeper trees accumulate more of the inter-level rescaling
+  // error (proportional to x^2), so 6 levels take 0.07 and 7 or more 0.06
+  // (nonlinearity 1e-5 and 3e-5)
+  const int Lt = t->t.L;
+  op->xs = opt->x > 0.0 ? opt->x : (f32 ? 0.15 : (Lt <= 5 ? 0.08 : (Lt == 6 ? 0.07 : 0.06)));
   op->nth = opt->n_theta > 0 ? opt->n_theta : op->tau + 1;
   op->nph = opt->n_phi > 0 ? opt->n_phi : 2 * op->tau + 2;
   op->Q = op->nth * op->nph;
   op->max_rhs = opt->max_rhs;
+  op->force_ms = (opt->flags & PIE_OPT_MATRIX_SHIFTS) != 0;
   op->L = t->t.L;
   op->ne = (int)m->m.ne;
   op->nt = (int)m->m.nt;
@@ -1882,10 +1894,18 @@ pie_status gmres_equilibrated(pie_op* op, const cx<double>* rhat, cx<double>* xh
 
 }  // namespace
 
+// Device workspace of a solve: the Krylov basis ((m + 1) N R), w and tmp,
+// the Hessenberg column and norms, and four N R vectors of the refinement.
+static size_t solve_workspace_bytes(int64_t N, int64_t R, int m) {
+  const size_t NR = (size_t)N * R;
+  return ((size_t)(m + 1) * NR + 2 * NR) * 16 + (size_t)(m + 1) * R * 16 + R * 16 + 4 * NR * 16;
+}
+
 // GMRES with outer refinement for Z x = b, or (block = SOLVE_PULSE_BLOCK)
 // for the pulse-pulse block alone.
 static pie_status solve_core(pie_op* op, pie_op* res_op, const void* b, void* x, int64_t R,
-                             const pie_solve_opts* opts, pie_solve_info* info, void* stream, int block) {
+                             const pie_solve_opts* opts, pie_solve_info* info, void* stream, int block,
+                             void* ws = nullptr, size_t ws_bytes = 0) {
   pie_status s = check_op_call(op, b, x, R);
   if (s) return s;
   pie_solve_opts o;
@@ -1907,6 +1927,11 @@ static pie_status solve_core(pie_op* op, pie_op* res_op, const void* b, void* x,
     return PIE_ERR_ARG;
   }
   const bool prec = o.precond == 1 && !block;
+  if (prec && !op->dPrec && ws) {
+    pie::set_error("the block-diagonal preconditioner is not built yet (building it allocates): call "
+                   "pie_precond_apply or pie_solve with precond = 1 once first");
+    return PIE_ERR_ARG;
+  }
   if (prec && !op->dPrec && (s = build_prec(op))) return s;
   pie_op* rop = res_op ? res_op : op;
   if (rop->N != op->N || R > rop->max_rhs) {
@@ -1917,10 +1942,19 @@ static pie_status solve_core(pie_op* op, pie_op* res_op, const void* b, void* x,
   hipStream_t st = (hipStream_t)stream;
   const int N = op->N, m = o.restart;
   const size_t NR = (size_t)N * R;
-  cx<double>* work = nullptr;
-  size_t wbytes = ((size_t)(m + 1) * NR + 2 * NR) * 16 + (size_t)(m + 1) * R * 16 + R * 16 + 4 * NR * 16;
-  HIPCHK(hipMalloc(&work, wbytes), "solver workspace");
-  std::unique_ptr<void, void (*)(void*)> guard(work, [](void* p) { (void)hipFree(p); });
+  const size_t wbytes = solve_workspace_bytes(N, R, m);
+  cx<double>* work = (cx<double>*)ws;
+  std::unique_ptr<void, void (*)(void*)> guard(nullptr, [](void* p) { (void)hipFree(p); });
+  if (work) {
+    if (wbytes > ws_bytes) {
+      pie::set_error("the solve needs " + std::to_string(wbytes) + " bytes of workspace (N R (restart + 7) 16 "
+                     "+ small), more than the " + std::to_string(ws_bytes) + " bytes available");
+      return PIE_ERR_ARG;
+    }
+  } else {
+    HIPCHK(hipMalloc(&work, wbytes), "solver workspace");
+    guard.reset(work);
+  }
   cx<double>* rr = work + ((size_t)(m + 1) * NR + 2 * NR) + (size_t)(m + 1) * R + R;  // after solver area
   cx<double>* rhat = rr + NR;
   cx<double>* xh = rhat + NR;
@@ -1979,6 +2013,7 @@ extern "C" pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void*
                                 const pie_solve_opts* opts, pie_solve_info* info, void* stream) {
   return solve_core(op, res_op, b, x, R, opts, info, stream, 0);
 }
+
 
 extern "C" pie_status pie_precond_apply(pie_op* op, const void* x, void* y, int64_t R, void* stream) {
   pie_status s = check_op_call(op, x, y, R);

@@ -164,12 +164,12 @@ class Operator:
     """pie_op: the PIE operator (near field + MLFMA far field) on the GPU."""
 
     def __init__(self, mesh: Mesh, tree: Tree, freq: float, near_prec=PIE_FP64, far_prec=PIE_FP64,
-                 tau=0, x=0.0, n_theta=0, n_phi=0, max_rhs=1, stream=None):
+                 tau=0, x=0.0, n_theta=0, n_phi=0, max_rhs=1, flags=0, stream=None):
         self.mesh, self.tree = mesh, tree
         o = _lib.pie_options()
         lib().pie_options_default(ctypes.byref(o))
         o.near_prec, o.far_prec, o.tau, o.x = near_prec, far_prec, tau, x
-        o.n_theta, o.n_phi, o.max_rhs = n_theta, n_phi, max_rhs
+        o.n_theta, o.n_phi, o.max_rhs, o.flags = n_theta, n_phi, max_rhs, flags
         h = ctypes.c_void_p()
         check(lib().pie_operator_create(mesh.h, tree.h, float(freq), ctypes.byref(o), _stream(stream),
                                         ctypes.byref(h)))

@@ -114,104 +114,117 @@ def test_batched_workload_sampled_rows():
 
 def test_gradient_workload_finite_differences():
     """Loss sum_r sum_d |F_r(d)|^2 over 16 plane waves with amplitudes a and
-    32 directions; autograd gradient (adjoint solve + adjoint far field)
-    against central differences along a random complex direction.  L is
-    quadratic in a, so a step of 1e-2 is exact up to the solves' accuracy.
-    At 1e-4 wavelength restarted GMRES stalls near a relative residual of
-    5e-5 on the pulse (n.A) rows: the charge mode [0; b_eq] has an eigenvalue
-    of order w^2 eps0.  The gradient's adjoint solve carries that residual
-    into the gradient (relative error of a few residuals), so the check is
-    held to 20 times the worst residual of the solves (1e-5 at least).  The
-    workload's step of 1e-6 moves L by ~6e-8 relative, below the ~1e-7 by
-    which the stalled solves perturb L, so at this size its difference is
-    printed, not asserted; the step-1e-6 and dense-oracle checks of the
-    same pipeline run where the solves converge (the 1280-triangle sphere
-    at 1e-4 wavelength in the parity suite)."""
+    32 directions on the 51 200-unknown sphere at 1e-4 wavelength; autograd
+    gradient (adjoint solve + adjoint far field) against central differences
+    along a random complex direction, at the workload's step h = 1e-6 and at
+    1e-2.  L is quadratic in a, so central differences are exact up to the
+    noise of L; at h = 1e-6 L moves by about 2e-6 relative, so L has to be
+    computed to ~1e-10.  That is checked with an FP64 operator whose
+    translation adds only ~1e-11 of rounding (tau = 4, x = 0.15; solves to
+    1e-10, so differences carry ~5e-5 of noise at h = 1e-6), to 2e-4 at
+    both steps: it tests the adjoint pipeline against its own forward
+    pipeline.  The default operator (tau = 7, x = 0.08, solve floor ~1e-6)
+    is checked at h = 1e-2 to 1e-3; its gradient against the dense oracle is
+    in test_gpu_lowfreq.py.  At 1e-4 wavelength the system's conditioning
+    (~1/(k h)) makes GMRES slow: the solves take thousands of iterations."""
     from paper_1806_04164_amd import autograd as ag
     w = synth.WORKLOADS["sphere_s5_1e-4lam_r16"]
     R = w.nrhs
     V, T = w.mesh()
     m = pie.Mesh(V, T)
     tr = pie.Tree(m, w.levels)
-    # tau = 6, x = 0.07: at 1e-4 wavelength the charge mode's eigenvalue is
-    # of order w^2 eps0, and the larger rounding amplification of the FP64
-    # default (tau = 7, x = 0.05) stalls GMRES near 5e-2; this pair keeps the
-    # floor near 5e-5 (its operator error, ~1e-3, is checked elsewhere)
-    op = pie.Operator(m, tr, w.freq, near_prec=PIE_FP64, far_prec=PIE_FP64, tau=6, x=0.07, max_rhs=R)
     kh, pol, _ = w.waves()
     dirs = synth.sphere_directions(32, 40)
-    kw = dict(tol=1e-10, restart=200, maxit=2000)
     a0 = np.ones(R, np.complex128)
-
-    worst = [0.0]
-
-    def loss(a_np, grad=False):
-        a = torch.tensor(a_np, dtype=torch.complex128, device="cuda", requires_grad=grad)
-        b = ag.plane_wave_rhs(op, kh, pol, a)
-        if grad:
-            x = ag.solve(op, b, **kw)
-        else:
-            x, info = op.solve(b.detach().contiguous(), **kw)
-            print("solve", info, flush=True)
-            assert info["rel_residual"] < 1e-3, info
-            worst[0] = max(worst[0], info["rel_residual"])
-        F = ag.farfield(op, x, dirs)
-        Lv = (F.abs() ** 2).sum()
-        if grad:
-            Lv.backward()
-            return Lv.item(), a.grad.cpu().numpy()
-        return Lv.item()
-
-    L0, g = loss(a0, grad=True)
     d = synth.complex_gaussian(R, 1, 41)[:, 0]
     d /= np.linalg.norm(d)
-    dd = float(np.real(np.vdot(g, d)))  # PyTorch convention: dL = Re(conj(g) . da)
-    for h in (1e-2, 1e-6):
-        fd = (loss(a0 + h * d) - loss(a0 - h * d)) / (2 * h)
-        tol = max(1e-5, 20 * worst[0])
-        print("h", h, "fd", fd, "grad.d", dd, "L", L0, "rel", abs(fd - dd) / abs(dd), "tol", tol, flush=True)
-        if h > 1e-3:
-            assert abs(fd - dd) <= tol * abs(dd)
+    for name, op, kw, steps in (
+            ("tau4", pie.Operator(m, tr, w.freq, near_prec=PIE_FP64, far_prec=PIE_FP64, tau=4, x=0.15, max_rhs=R),
+             dict(tol=1e-10, restart=500, maxit=20000), ((1e-6, 2e-4), (1e-2, 2e-4))),
+            ("default", pie.Operator(m, tr, w.freq, near_prec=PIE_FP64, far_prec=PIE_FP64, max_rhs=R),
+             dict(tol=2e-6, restart=500, maxit=12000), ((1e-2, 1e-3),))):
+
+        def loss(a_np, grad=False):
+            a = torch.tensor(a_np, dtype=torch.complex128, device="cuda", requires_grad=grad)
+            b = ag.plane_wave_rhs(op, kh, pol, a)
+            if grad:
+                x = ag.solve(op, b, **kw)
+            else:
+                x, info = op.solve(b.detach().contiguous(), **kw)
+                assert info["converged"], info
+            F = ag.farfield(op, x, dirs)
+            Lv = (F.abs() ** 2).sum()
+            if grad:
+                Lv.backward()
+                return Lv.item(), a.grad.cpu().numpy()
+            return Lv.item()
+
+        L0, g = loss(a0, grad=True)
+        print(name, "solves", ag.PieSolve.last_info, flush=True)
+        dd = float(np.real(np.vdot(g, d)))  # PyTorch convention: dL = Re(conj(g) . da)
+        for h, tol in steps:
+            fd = (loss(a0 + h * d) - loss(a0 - h * d)) / (2 * h)
+            rel = abs(fd - dd) / abs(dd)
+            print(name, "h", h, "fd", fd, "grad.d", dd, "L", L0, "rel", rel, flush=True)
+            assert rel <= tol
 
 
-def test_uneven_batch_one_launch():
+def test_uneven_batch_solves():
+    """The uneven batch's solve (each of the eight spheres, 12 800 to
+    3 276 800 unknowns, 1e-5 to 1e-1 wavelength, 8 plane waves): GMRES on
+    the mixed operator (FP32 near field) with FP64 residual refinement, far
+    fields against the Mie series.  Refinement steps are driven from here
+    (one correction per call, at most 1000 inner iterations) so that every
+    call is bounded and reports.  Objects 0-6 go to a relative residual of
+    2e-5 (the 7-level trees' rounding floor is about 1e-5) and are held to
+    the icosphere's discretisation error (3e-3 at subdivision 4, 1e-3
+    above; cf. the 100 MHz sweep below).  The 3 276 800-unknown sphere at
+    1.5e-5 wavelength (conditioning ~1e7) gets two steps; its residual and
+    far-field error are reported and held to 1e-2.  At these frequencies
+    GMRES needs thousands of iterations (the conditioning grows as 1/(k h)):
+    a preconditioner for closed surfaces is the missing piece."""
+    from oracle import mie
     objs = synth.uneven_batch()
-    R = 8
-    ops, xs, ys, keep = [], [], [], []
+    th = np.linspace(0.0, np.pi, 19)
+    dirs = np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
     for i, w in enumerate(objs):
         V, T = w.mesh()
         m = pie.Mesh(V, T)
         tr = pie.Tree(m, w.levels)
-        op = pie.Operator(m, tr, w.freq, near_prec=PIE_FP32, far_prec=PIE_FP64, max_rhs=R)
-        x = torch.from_numpy(synth.complex_gaussian(op.N, R, 60 + i)).cuda()
-        ops.append(op)
-        xs.append(x)
-        ys.append(torch.empty_like(x))
-        keep.append((m, tr))
-        print("object", i, w.subdiv, f"{w.d_over_lambda:.2e}", op.N, flush=True)
-    g = pie.BatchGraph(ops, xs, ys)
-    for rep in range(2):
-        for y in ys:
-            y.zero_()
-        g.launch()
-        torch.cuda.synchronize()
-        for op, x, y in zip(ops, xs, ys):
-            assert torch.equal(y, op.matvec(x)), rep
-    # sampled oracle rows of every object (one RWG and one pulse row for the
-    # two largest, two of each otherwise)
-    jobs, rows_of = [], []
-    for i, (w, op) in enumerate(zip(objs, ops)):
-        E = keep[i][0].sizes()[0]
-        n = 1 if w.subdiv >= 8 else 2
-        rows = _rows(op.N, E, n, n, 70 + i)
-        rows_of.append((rows, E))
-        jobs.append((("uneven", i), w.freq, rows, 60 + i, R))
-    refs = sampled_rows(jobs)
-    for i, (ref, (rows, E)) in enumerate(zip(refs, rows_of)):
-        x = xs[i].cpu().numpy()
-        errs = _block_errors(_gpu_blocks(ops[i], x, rows, E, use_graph=False), ref, rows, E)
-        print("object", i, errs, flush=True)
-        assert max(errs.values()) <= 1e-3
+        R = w.nrhs
+        fast = pie.Operator(m, tr, w.freq, near_prec=PIE_FP32, far_prec=PIE_FP64, max_rhs=R)
+        ref = pie.Operator(m, tr, w.freq, near_prec=PIE_FP64, far_prec=PIE_FP64, max_rhs=R)
+        kh, pol, amp = w.waves()
+        b = ref.rhs_planewave(kh, pol, amp)
+        big = w.subdiv >= 8
+        x, total = None, 0
+        for step in range(2 if big else 12):
+            x, info = fast.solve(b, x=x, res_op=ref, tol=2e-5, inner_tol=1e-3, refine=2,
+                                 restart=60 if big else 150, maxit=1000)
+            total += info["iterations"]
+            print("object", i, "step", step, info, flush=True)
+            if info["converged"]:
+                break
+        F = ref.farfield(x, dirs).cpu().numpy()
+        k = 2.0 * np.pi * w.freq / synth.C0
+        err = 0.0
+        for r in range(R):
+            # the Mie far field for incidence khat_r, polarisation pol_r: rotate
+            # the observation directions into the frame (pol, khat x pol, khat)
+            e1, e3 = pol[r], kh[r]
+            e2 = np.cross(e3, e1)
+            Rm = np.stack([e1, e2, e3], 0)
+            Fm = mie.farfield(k * synth.DIAMETER / 2, k, dirs @ Rm.T) @ Rm
+            err = max(err, np.linalg.norm(F[r] - Fm) / np.linalg.norm(Fm))
+        print("object", i, w.subdiv, f"{w.d_over_lambda:.2e}", ref.N, "iterations", total, "residual",
+              info["rel_residual"], "far field vs Mie", err, flush=True)
+        if big:
+            assert err < 1e-2
+        else:
+            assert info["converged"]
+            assert err < (3e-3 if w.subdiv == 4 else 1e-3)
+        del fast, ref, x, b
+        torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("sub,tol", [(4, 3e-3), (5, 1e-3)])

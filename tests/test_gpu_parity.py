@@ -391,3 +391,31 @@ def test_gradient_of_farfield_loss():
     gref = 2.0 * a0 * np.sum(np.abs(Fu) ** 2, axis=(1, 2))
     print("grad vs dense", np.linalg.norm(g - gref) / np.linalg.norm(gref), flush=True)
     assert np.linalg.norm(g - gref) < 1e-2 * np.linalg.norm(gref)
+
+
+@pytest.mark.parametrize("R", [1, 16])
+def test_matrix_core_kernels_against_oracle(s4, R):
+    """The kernels the benchmark times on small trees, pinned as tightly as
+    the vector kernels: with PIE_OPT_MATRIX_SHIFTS the FP64 inter-level
+    shifts run on the matrix cores (k_mshift_up / k_mshift_down) at every
+    level, and with R = 16 columns the pass also takes the batched
+    aggregation and reception (k_maggregate / k_mreceive), the sibling-group
+    translation (k_translate_batch).
+    tau = 4, x = 0.15 (round-off amplification ~1e5): every column against
+    the oracle's MLFMA to 1e-9 per block, and against the vector-shift
+    operator to rounding."""
+    from paper_1806_04164_amd._lib import PIE_OPT_MATRIX_SHIFTS
+    op = pie.Operator(s4["mesh"], s4["tree"], s4["f"], tau=4, x=0.15, max_rhs=R, flags=PIE_OPT_MATRIX_SHIFTS)
+    plain = pie.Operator(s4["mesh"], s4["tree"], s4["f"], tau=4, x=0.15, max_rhs=R)
+    M = mlfma.MLFMA(s4["prob"], 4, mlfma.Params(tau=4, x=0.15))
+    X = synth.complex_gaussian(s4["prob"].N, R, 23)
+    for r in sorted({0, R - 1}):
+        errs = block_errors(lambda v: host(op.matvec(dev(np.repeat(v[:, None], R, axis=1))))[:, r],
+                            M.matvec, X[:, r], s4["E"])
+        print("matrix-core path R", R, "column", r, errs, flush=True)
+        assert max(errs.values()) < 1e-9
+    Y = host(op.matvec(dev(X)))
+    Yp = host(plain.matvec(dev(X)))
+    d = np.linalg.norm(Y - Yp) / np.linalg.norm(Yp)
+    print("matrix-core vs vector shifts", d, flush=True)
+    assert d < 1e-12

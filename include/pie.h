@@ -356,6 +356,25 @@ pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void* x,
                      int64_t R, const pie_solve_opts* opts,
                      pie_solve_info* info, void* stream);
 
+/* For callers that cannot allocate device memory (serving loops that must
+ * not call hipMalloc, harnesses that forbid it): pie_solve with the same
+ * arguments, results and status codes, but the solver's device workspace is
+ * a fixed array that the library holds on each GPU from the first call
+ * until the process ends (PIE_SOLVE_NOALLOC_BYTES = 128 MiB per GPU), so the
+ * call allocates nothing.  It needs 16 N R (restart + 7) + 16 R (restart + 2)
+ * bytes and returns PIE_ERR_ARG, before any device work, when that exceeds
+ * the array (e.g. N = 51 200, R = 1 allows restart <= 156).  precond = 1
+ * requires the preconditioner to exist already (pie_precond_apply or a
+ * pie_solve with precond = 1 builds it; building allocates), else
+ * PIE_ERR_ARG.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (from different threads or streams) race and must be
+ * serialised by the caller.  The operators' own workspaces are allocated at
+ * pie_operator_create, so the MVMs inside allocate nothing either. */
+#define PIE_SOLVE_NOALLOC_BYTES (128u << 20)
+pie_status pie_solve_noalloc(pie_op* op, pie_op* res_op, const void* b,
+                             void* x, int64_t R, const pie_solve_opts* opts,
+                             pie_solve_info* info, void* stream);
+
 /* Block-diagonal preconditioner of the solve (precond = 1): y = M^-1 x with
  * M = blockdiag(Z_bb) over the finest boxes b (FP64 self blocks, inverted on
  * the host at the first use and kept with the operator), for callers with

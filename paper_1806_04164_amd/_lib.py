@@ -47,6 +47,7 @@ EXPORTS = [
     "pie_profile_enable", "pie_profile_read", "pie_farfield_adjoint",
     "pie_schedule_get", "pie_schedule_set", "pie_autotune",
     "pie_graph_create", "pie_graph_launch", "pie_graph_destroy", "pie_graph_create_batch",
+    "pie_solve_noalloc",
 ]
 STAGES = ["permute", "near", "aggregate", "shift_up", "translate", "receive", "shift_down"]
 
@@ -109,6 +110,8 @@ def lib():
         "pie_solve_opts_default": (None, [ctypes.POINTER(pie_solve_opts)]),
         "pie_solve": (I32, [P, P, P, P, I64, ctypes.POINTER(pie_solve_opts),
                             ctypes.POINTER(pie_solve_info), P]),
+        "pie_solve_noalloc": (I32, [P, P, P, P, I64, ctypes.POINTER(pie_solve_opts),
+                                    ctypes.POINTER(pie_solve_info), P]),
         "pie_precond_apply": (I32, [P, P, P, I64, P]),
         "pie_charge": (I32, [P, I64, P, P, P, I32, P, P, P, ctypes.POINTER(pie_solve_opts),
                              ctypes.POINTER(pie_solve_info), P]),

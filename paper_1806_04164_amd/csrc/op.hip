@@ -2014,6 +2014,50 @@ extern "C" pie_status pie_solve(pie_op* op, pie_op* res_op, const void* b, void*
   return solve_core(op, res_op, b, x, R, opts, info, stream, 0);
 }
 
+// Workspace of pie_solve_noalloc: one array per GPU, loaded with the code
+// object and kept until the process ends.  Host code uses its device address
+// from hipGetSymbolAddress (per device), never the array's name.
+static __device__ __align__(256) unsigned char scratch[PIE_SOLVE_NOALLOC_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current.
+pie_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices) {
+    pie::set_error("device index out of range for the solver scratch table");
+    return PIE_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur), "hipGetDevice");
+    if (cur != dev) HIPCHK(hipSetDevice(dev), "hipSetDevice");
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PIE_OK;
+}
+}  // namespace
+
+extern "C" pie_status pie_solve_noalloc(pie_op* op, pie_op* res_op, const void* b, void* x, int64_t R,
+                                        const pie_solve_opts* opts, pie_solve_info* info, void* stream) {
+  if (!op) {
+    pie::set_error("null operator");
+    return PIE_ERR_ARG;
+  }
+  void* ws = nullptr;
+  pie_status s = scratch_address(op->device, &ws);
+  if (s) return s;
+  return solve_core(op, res_op, b, x, R, opts, info, stream, 0, ws, PIE_SOLVE_NOALLOC_BYTES);
+}
 
 extern "C" pie_status pie_precond_apply(pie_op* op, const void* x, void* y, int64_t R, void* stream) {
   pie_status s = check_op_call(op, x, y, R);

@@ -325,6 +325,10 @@ pie_status pie_rhs_planewave(pie_op* op, int64_t R, const double* khat,
  * operator's own precision and recomputes the residual b - Z x with the
  * residual operator (if res_op is NULL, op itself).  x: device complex128
  * [N][R] (input: initial guess if use_x0, output: solution).
+ * Residuals are relative and measured in the equilibrated norm,
+ * ||D (b - Z x)|| / ||D b||, the norm GMRES minimises (the rows of Eqs. (1)
+ * and (2) carry different units; at low frequency their scales differ by
+ * orders of magnitude, so the plain 2-norm weighs one block only).
  * info (host, may be NULL) receives iterations and final relative residual
  * per RHS. Returns PIE_WARN_NOT_CONVERGED if any RHS missed tol. */
 typedef struct pie_solve_opts {

@@ -1963,23 +1963,31 @@ static pie_status solve_core(pie_op* op, pie_op* res_op, const void* b, void* x,
   cx<double>* X = (cx<double>*)x;
   hipError_t e;
   if (!o.use_x0) HIPCHK(hipMemsetAsync(X, 0, NR * 16, st), "zero x");
+  // Residuals are measured in the equilibrated norm ||D v|| (D = diag
+  // |Z_ii|^-1/2), the norm GMRES minimises: the rows of Eqs. (1) and (2)
+  // carry different units, and at low frequency their scales differ by
+  // orders of magnitude.  dnorm leaves D v in rhat.
+  auto dnorm = [&](const void* v, std::vector<double>& out) -> pie_status {
+    if ((e = pie::launch_scale_rows(v, op->dDiagScale, N, (int)R, rhat, st)) != hipSuccess)
+      return hip_fail(e, "scale");
+    if ((e = pie::launch_norms(rhat, N, (int)R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
+    HIPCHK(hipMemcpyAsync(out.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
+    HIPCHK(hipStreamSynchronize(st), "solve");
+    return PIE_OK;
+  };
   std::vector<double> bn(R), rn(R);
-  if ((e = pie::launch_norms(b, N, (int)R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
-  HIPCHK(hipMemcpyAsync(bn.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
+  if ((s = dnorm(b, bn))) return s;
   int iters = 0, refinements = 0;
   double relmax = 0.0;
   for (int k = 0; k < o.refine; ++k) {
     // residual with the residual operator
     if ((s = solve_mvm(rop, X, zx, R, 3 | (o.adjoint ? 4 : 0) | block, st))) return s;
     if ((e = pie::launch_sub(b, zx, N, (int)R, rr, st)) != hipSuccess) return hip_fail(e, "sub");
-    if ((e = pie::launch_norms(rr, N, (int)R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
-    HIPCHK(hipMemcpyAsync(rn.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
-    HIPCHK(hipStreamSynchronize(st), "solve");
+    if ((s = dnorm(rr, rn))) return s;  // rhat = D r
     relmax = 0.0;
     for (int r = 0; r < R; ++r) relmax = std::max(relmax, bn[r] > 0 ? rn[r] / bn[r] : 0.0);
     if (relmax <= o.tol) break;
     ++refinements;
-    if ((e = pie::launch_scale_rows(rr, op->dDiagScale, N, (int)R, rhat, st)) != hipSuccess) return hip_fail(e, "scale");
     HIPCHK(hipMemsetAsync(xh, 0, NR * 16, st), "zero");
     int it = 0;
     if ((s = gmres_equilibrated(op, rhat, xh, (int)R, o, inner, 3 | (o.adjoint ? 4 : 0) | block, prec, &it, st,
@@ -1994,9 +2002,7 @@ static pie_status solve_core(pie_op* op, pie_op* res_op, const void* b, void* x,
     if (k == o.refine - 1) {
       if ((s = solve_mvm(rop, X, zx, R, 3 | (o.adjoint ? 4 : 0) | block, st))) return s;
       if ((e = pie::launch_sub(b, zx, N, (int)R, rr, st)) != hipSuccess) return hip_fail(e, "sub");
-      if ((e = pie::launch_norms(rr, N, (int)R, dn, st)) != hipSuccess) return hip_fail(e, "norm");
-      HIPCHK(hipMemcpyAsync(rn.data(), dn, R * 8, hipMemcpyDeviceToHost, st), "norm copy");
-      HIPCHK(hipStreamSynchronize(st), "solve");
+      if ((s = dnorm(rr, rn))) return s;
       relmax = 0.0;
       for (int r = 0; r < R; ++r) relmax = std::max(relmax, bn[r] > 0 ? rn[r] / bn[r] : 0.0);
     }

@@ -330,11 +330,9 @@ def test_gradient_of_farfield_loss():
     on an FP64 operator with tau = 4, x = 0.15 (round-off ~1e-11); the
     step-1e-6 differences are printed for reference.
     (2) Against the dense-oracle closed form 2 a_r ||F_r(unit)||^2 (L
-    decouples over r) with the default operator.  At D = 1e-4 lambda the far
-    field is an O(ka) residue of a current dominated by non-radiating loop
-    currents, so the MLFMA's ~1e-3 operator error shows up as 6.7e-2 in F and
-    6e-3 in sum |F|^2 -- the oracle's own MLFMA gives the same numbers -- so
-    the bound here is 1e-2."""
+    decouples over r) with the default operator: 2e-4 measured, 1e-3
+    asserted (the operator keeps the loop/charge structure of the dense
+    matrix, so its ~5e-4 error is not amplified by the conditioning)."""
     from paper_1806_04164_amd import autograd as ag
     V, T = synth.icosphere(3)
     f = 1e-4 * synth.C0 / synth.DIAMETER
@@ -344,7 +342,10 @@ def test_gradient_of_farfield_loss():
     kh, pol, _ = synth.plane_waves(R, 4)
     dirs = synth.sphere_directions(8, 40)
     a0 = np.array([1.0, 0.7 - 0.2j, -0.3 + 0.9j, 0.5j])
-    kw = dict(tol=1e-8, restart=300, maxit=8000)
+    # refinement: GMRES stops on the equilibrated residual; the outer steps
+    # recompute the unscaled one (the adjoint right-hand side lives on the RWG
+    # rows only, whose scaling differs most from the pulse rows')
+    kw = dict(tol=1e-8, restart=300, maxit=8000, refine=4)
 
     def loss(op, a_np, grad=False):
         a = torch.tensor(a_np, dtype=torch.complex128, device="cuda", requires_grad=grad)
@@ -380,8 +381,10 @@ def test_gradient_of_farfield_loss():
     e6 = np.linalg.norm(g4 - fd6) / np.linalg.norm(fd6)
     print("grad", g4, "fd(1e-2)", fd2, "rel err", e2, "fd(1e-6) rel err", e6, flush=True)
     assert e2 < 1e-4
-    # dense oracle closed form, default FP64 operator
+    # dense oracle closed form, default FP64 operator (its solves stop at
+    # 5e-6, above the ~3e-6 floor of its translation rounding)
     op = pie.Operator(m, tr, f, max_rhs=R)
+    kw.update(tol=5e-6)
     _, g = loss(op, a0, grad=True)
     prob = mom.Problem(V, T, f)
     Z = prob.dense()
@@ -390,7 +393,7 @@ def test_gradient_of_farfield_loss():
     Fu = prob.farfield(Xu, dirs)                       # [R, nd, 3]
     gref = 2.0 * a0 * np.sum(np.abs(Fu) ** 2, axis=(1, 2))
     print("grad vs dense", np.linalg.norm(g - gref) / np.linalg.norm(gref), flush=True)
-    assert np.linalg.norm(g - gref) < 1e-2 * np.linalg.norm(gref)
+    assert np.linalg.norm(g - gref) < 1e-3 * np.linalg.norm(gref)
 
 
 @pytest.mark.parametrize("R", [1, 16])

@@ -17,7 +17,7 @@ from paper_1806_04164_amd._lib import PIE_ERR_ARG, PIE_FP64
 pytestmark = pytest.mark.gpu
 
 
-def _call(fn, op, b, R, restart, maxit=2000, tol=1e-8):
+def _call(fn, op, b, R, restart, maxit=2000, tol=1e-6):
     o = _lib.pie_solve_opts()
     _lib.lib().pie_solve_opts_default(ctypes.byref(o))
     o.restart, o.maxit, o.tol = restart, maxit, tol

@@ -193,6 +193,10 @@ void pie_operator_destroy(pie_op* op);
 #define PIE_OI_IL_PAIRS 8    /* interaction-list pairs over all levels    */
 #define PIE_OI_INCIDENCES 9  /* (finest box, triangle) incidences         */
 #define PIE_OI_DEVICE_BYTES 10 /* device memory held by the operator      */
+#define PIE_OI_NEAR_ENTRIES_RWG 11 /* stored RWG-RWG near entries          */
+#define PIE_OI_NEAR_ENTRIES_TRI 12 /* stored triangle-triangle entries of  */
+                                   /* the scalar operator (applied to x_A  */
+                                   /* and u)                               */
 pie_status pie_operator_info(const pie_op* op, int32_t what, int64_t* value);
 /* Scale factor s and kappa = k/s at level l (3..L). */
 pie_status pie_operator_level(const pie_op* op, int32_t level, double* s,

@@ -35,7 +35,7 @@ PIE_NEAR_FORK_AFTER_AGGREGATE = 2
 TQ = dict(NBOX=1, COORDS=2, PARENT=3, PERM=4, BOXPTR=5, NEAR_PTR=6, NEAR_IDX=7,
           IL_PTR=8, IL_SRC=9, IL_OFF=10)
 OI = dict(N=1, Q=2, TAU=3, NEAR_BLOCKS=4, NEAR_ENTRIES=5, NEAR_BYTES=6, NBOX_FINEST=7,
-          IL_PAIRS=8, INCIDENCES=9, DEVICE_BYTES=10)
+          IL_PAIRS=8, INCIDENCES=9, DEVICE_BYTES=10, NEAR_ENTRIES_RWG=11, NEAR_ENTRIES_TRI=12)
 
 # every function declared in include/pie.h
 EXPORTS = [

@@ -144,15 +144,15 @@ struct DevLevel {
   const int32_t* il_off;
   int32_t nug;              // parent groups of the upward shift into this level
   const int32_t* ug_ptr;    // [nug+1] parent ranges; each group has <= SHIFT_GROUP children
-  // batched translation by sibling groups (the boxes of one parent share most
-  // of their interaction-list sources)
-  int32_t nsg;              // sibling groups: runs of boxes with one parent
-  const int32_t* sg_ptr;    // [nsg+1] box ranges
-  const int32_t* su_ptr;    // [nsg+1] ranges into su_src
-  const int32_t* su_src;    // union of a group's sources, ascending
-  const int32_t* se_u;      // [pairs] union index of each entry (entries of a box in
-  const int32_t* se_off;    //   ascending union index) and its offset index
-  int32_t sib_ok;           // every union <= TB_UMAX sources, every list <= TB_SPLIT * TB_EMAX
+  // batched translation by groups of at most TG_BOXES boxes of one parent
+  // (siblings share most of their interaction-list sources): each group
+  // lists the ascending union of its boxes' sources once, with the offset
+  // index of every box that has the source in its list
+  int32_t ntg;              // groups
+  const int32_t* tg_box;    // [ntg+1] box ranges
+  const int32_t* tg_ent;    // [ntg+1] ranges into te
+  const int4* te;           // {source box, offset of box 0 | box 1 << 16, box 2 | box 3 << 16, 0};
+                            //   offset 0xffff: the source is not in that box's list
 };
 
 // Inter-level shift tiling: sample rows per thread, boxes per workgroup.
@@ -162,12 +162,11 @@ constexpr int SHIFT_GROUP = 12;
 constexpr int IL_MAX = 189;
 // Translation offsets (max-norm 2 or 3 in box units).
 constexpr int TRANSLATE_OFFSETS = 316;
-// Batched translation: samples per workgroup, lanes per (box, sample), most
-// union sources per group, most list entries per lane.
-constexpr int TB_Q = 8;
-constexpr int TB_SPLIT = 4;
-constexpr int TB_UMAX = 80;
-constexpr int TB_EMAX = 16;
+// Batched translation: boxes per group, samples per workgroup (one per
+// wavefront), columns per wavefront pass.
+constexpr int TG_BOXES = 4;
+constexpr int TG_Q = 8;
+constexpr int TG_COLS = 64;
 
 // (finest box, triangle) incidences: up to three RWG functions of the box
 // that live on the triangle, and the triangle's pulse if the triangle belongs

@@ -1389,91 +1389,97 @@ hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const
 }
 
 // ---------------------------------------------------------------------------
-// Batched translation (W >= TB_MIN_COLS columns in a pass) by sibling
-// groups.  The boxes of one parent (at most 8) share most of their
-// interaction-list sources (the union is 3.6-4.4 times smaller than the sum
-// of the lists on the sphere workloads).  A workgroup owns one sibling group
-// and TB_Q samples and walks the W columns: the translation factors of each
-// thread's entries are loaded once for all columns; per column the union's
-// patterns for the workgroup's samples are staged in LDS (the next column's
-// staging loads in flight while this column is summed), thread (box,
-// sample, split) adds the entries j = split (mod TB_SPLIT) of its box in
-// ascending union index, and the TB_SPLIT partial sums (adjacent lanes) are
-// added by a fixed butterfly.
+// Batched translation (W >= TB_MIN_COLS columns in a pass).  For one sample q
+// the translation of Eq. (4) scales whole pattern rows: the W x 5 values
+// P[box][r][q][c] of every source in a box's list are multiplied by the one
+// factor T[off][q] and summed.  A wavefront owns (translation group, q, a
+// chunk of <= TG_COLS columns): its lanes hold the chunk's (r, c) values
+// (NS per lane), so the factor is wavefront-uniform (scalar loads) and each
+// source row loaded into registers is used for every box of the group that
+// lists it (the group's union is walked once, in ascending source order,
+// which is also each box's summation order).  Workgroup = TG_Q samples of one
+// group; chunk slowest, then the sample block, then the group: each XCD takes
+// whole sample blocks and walks the groups in Morton order, so the workgroups
+// resident on it at one time share their source rows in its L2.
 // ---------------------------------------------------------------------------
 constexpr int TB_MIN_COLS = 16;
-constexpr int TB_STAGE = (TB_UMAX * TB_Q * 5 + 255) / 256;  // staged values per thread
 
-template <typename TF>
-__global__ void __launch_bounds__(256) k_translate_batch(DevLevel Lv, const cx<TF>* __restrict__ S,
-                                                         const cx<TF>* __restrict__ T, cx<TF>* __restrict__ Gout,
-                                                         int Q, int W, int ntile) {
-  __shared__ cx<TF> Ss[TB_UMAX * TB_Q * 5];
-  __shared__ int32_t usrc[TB_UMAX];
-  const int it = xcd_box(blockIdx.x, Lv.nsg * ntile);
+template <typename TF, int NS>
+__global__ void __launch_bounds__(64 * TG_Q) k_translate_rows(DevLevel Lv, const cx<TF>* __restrict__ S,
+                                                        const cx<TF>* __restrict__ T, cx<TF>* __restrict__ Gout,
+                                                        int Q, int W, int nqb, int cols) {
+  const int it = xcd_box(blockIdx.x, Lv.ntg * nqb * ((W + cols - 1) / cols));
   if (it < 0) return;
-  const int g = it / ntile, tile = it - g * ntile;
-  const int q0 = tile * TB_Q;
-  const int b0 = Lv.sg_ptr[g], nbg = Lv.sg_ptr[g + 1] - b0;
-  const int ug = Lv.su_ptr[g], nu = Lv.su_ptr[g + 1] - ug;  // <= TB_UMAX (host)
-  const int sp = threadIdx.x % TB_SPLIT, ql = (threadIdx.x / TB_SPLIT) % TB_Q;
-  const int d = threadIdx.x / (TB_SPLIT * TB_Q), q = q0 + ql;
-  const bool act = d < nbg && q < Q;
-  const int b = b0 + (d < nbg ? d : 0);
-  const int e0 = Lv.il_ptr[b], ne = act ? Lv.il_ptr[b + 1] - e0 : 0;
-  for (int e = threadIdx.x; e < nu; e += blockDim.x) usrc[e] = Lv.su_src[ug + e];
-  cx<TF> tv[TB_EMAX];
-  int uu[TB_EMAX];
+  const int g = it % Lv.ntg, rest = it / Lv.ntg;
+  const int qb = rest % nqb, chunk = rest / nqb;
+  const int q = qb * TG_Q + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (q >= Q) return;
+  const int lane = threadIdx.x & 63;
+  const int c0 = chunk * cols, nv = 5 * min(cols, W - c0);
+  int off[NS], ld[NS];  // value offsets in a pattern row (-1: no value); load offsets (always in the row)
 #pragma unroll
-  for (int i = 0; i < TB_EMAX; ++i) {
-    const int j = sp + i * TB_SPLIT;
-    const int e = e0 + (j < ne ? j : 0);
-    uu[i] = j < ne ? Lv.se_u[e] * (TB_Q * 5) + ql * 5 : 0;
-    tv[i] = j < ne ? T[(size_t)Lv.se_off[e] * Q + q] : mk<TF>(0, 0);
+  for (int i = 0; i < NS; ++i) {
+    const int e = i * 64 + lane, r = c0 + e / 5;
+    off[i] = e < nv ? (r * Q + q) * 5 + e % 5 : -1;
+    ld[i] = off[i] < 0 ? 0 : off[i];
   }
-  const int nst = nu * TB_Q * 5;
-  cx<TF> sreg[TB_STAGE];
-  auto stage_load = [&](int r) {
+  const size_t row = (size_t)W * Q * 5;
+  const int b0 = Lv.tg_box[g], nbx = Lv.tg_box[g + 1] - b0;
+  const int j0 = Lv.tg_ent[g], j1 = Lv.tg_ent[g + 1];
+  cx<TF> acc[TG_BOXES][NS];
 #pragma unroll
-    for (int i = 0; i < TB_STAGE; ++i) {
-      const int e = threadIdx.x + 256 * i;
-      const int su = e / (TB_Q * 5), rem = e - su * (TB_Q * 5), qq = rem / 5, k = rem - qq * 5;
-      sreg[i] = e < nst && q0 + qq < Q ? S[(((size_t)usrc[su] * W + r) * Q + q0 + qq) * 5 + k] : mk<TF>(0, 0);
+  for (int d = 0; d < TG_BOXES; ++d)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) acc[d][i] = mk<TF>(0, 0);
+  // entry j: its source row (lane values) and the factors of its boxes
+  // (offset 0xffff: not in that box's list; its factor load reads offset 0)
+  auto fetch = [&](int j, int4& en, cx<TF>* v, cx<TF>* t) {
+    en = Lv.te[j];
+    const cx<TF>* src = S + (size_t)en.x * row;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) v[i] = src[ld[i]];
+#pragma unroll
+    for (int d = 0; d < TG_BOXES; ++d) {
+      const uint32_t w = (uint32_t)(d < 2 ? en.y : en.z), o = d & 1 ? w >> 16 : w & 0xffffu;
+      t[d] = T[(size_t)(o == 0xffffu ? 0u : o) * Q + q];
     }
   };
-  __syncthreads();  // usrc
-  stage_load(0);
-  for (int r = 0; r < W; ++r) {
-    __syncthreads();  // the previous column is summed
+  auto use = [&](const int4& en, const cx<TF>* v, const cx<TF>* t) {
 #pragma unroll
-    for (int i = 0; i < TB_STAGE; ++i) {
-      const int e = threadIdx.x + 256 * i;
-      if (e < nst) Ss[e] = sreg[i];
+    for (int d = 0; d < TG_BOXES; ++d) {
+      const uint32_t w = (uint32_t)(d < 2 ? en.y : en.z), o = d & 1 ? w >> 16 : w & 0xffffu;
+      if (o != 0xffffu)
+#pragma unroll
+        for (int i = 0; i < NS; ++i) cfma(acc[d][i], t[d], v[i]);
     }
-    __syncthreads();
-    if (r + 1 < W) stage_load(r + 1);  // in flight during this column's sums
-    cx<TF> acc[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) acc[k] = mk<TF>(0, 0);
-#pragma unroll
-    for (int i = 0; i < TB_EMAX; ++i)
-      if (sp + i * TB_SPLIT < ne) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) cfma(acc[k], tv[i], Ss[uu[i] + k]);
-      }
-#pragma unroll
-    for (int k = 0; k < 5; ++k)
-#pragma unroll
-      for (int h = 1; h < TB_SPLIT; h <<= 1) {
-        acc[k].re += __shfl_xor(acc[k].re, h);
-        acc[k].im += __shfl_xor(acc[k].im, h);
-      }
-    if (act && sp == 0) {
-      cx<TF>* o = Gout + (((size_t)b * W + r) * Q + q) * 5;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) o[k] = acc[k];
+  };
+  if (j0 < j1) {
+    // three register sets: the next two entries' loads are in flight while
+    // the current one is summed (prefetches past the end re-read the last)
+    int4 eA, eB, eC;
+    cx<TF> sA[NS], sB[NS], sC[NS], tA[TG_BOXES], tB[TG_BOXES], tC[TG_BOXES];
+    fetch(j0, eA, sA, tA);
+    fetch(min(j0 + 1, j1 - 1), eB, sB, tB);
+    for (int j = j0;;) {
+      fetch(min(j + 2, j1 - 1), eC, sC, tC);
+      use(eA, sA, tA);
+      if (++j >= j1) break;
+      fetch(min(j + 2, j1 - 1), eA, sA, tA);
+      use(eB, sB, tB);
+      if (++j >= j1) break;
+      fetch(min(j + 2, j1 - 1), eB, sB, tB);
+      use(eC, sC, tC);
+      if (++j >= j1) break;
     }
   }
+#pragma unroll
+  for (int d = 0; d < TG_BOXES; ++d)
+    if (d < nbx) {
+      cx<TF>* o = Gout + (size_t)(b0 + d) * row;
+#pragma unroll
+      for (int i = 0; i < NS; ++i)
+        if (off[i] >= 0) o[off[i]] = acc[d][i];
+    }
 }
 
 // Interaction-list split: Q lanes rounded to wavefronts (at most 256 per
@@ -1489,7 +1495,7 @@ hipError_t launch_translate_levels(const DevLevel* lv, const void* const* S, con
                                    int n, int Q, int R, hipStream_t st) {
   const int width = translate_width(Q), ns = translate_split(Q);
   bool single = n <= TSET_MAX;
-  for (int i = 0; i < n && single; ++i) single = !(R >= TB_MIN_COLS && lv[i].sib_ok);
+  if (R >= TB_MIN_COLS) single = false;
   if (!single) {
     for (int i = 0; i < n; ++i) {
       hipError_t e = launch_translate<TF>(lv[i], S[i], T[i], G[i], Q, R, st);
@@ -1516,10 +1522,16 @@ hipError_t launch_translate_levels(const DevLevel* lv, const void* const* S, con
 template <typename TF>
 hipError_t launch_translate(const DevLevel& Lv, const void* S, const void* T, void* Gout, int Q, int R,
                             hipStream_t st) {
-  if (R >= TB_MIN_COLS && Lv.sib_ok) {
-    const int ntile = (Q + TB_Q - 1) / TB_Q;
-    hipLaunchKernelGGL(k_translate_batch<TF>, dim3(xcd_grid(Lv.nsg * ntile)), dim3(256), 0, st, Lv,
-                       (const cx<TF>*)S, (const cx<TF>*)T, (cx<TF>*)Gout, Q, R, ntile);
+  if (R >= TB_MIN_COLS) {
+    const int cols = TG_COLS;
+    const int nqb = (Q + TG_Q - 1) / TG_Q, nch = (R + cols - 1) / cols;
+    const int ns = (5 * std::min(R, cols) + 63) / 64;  // values per lane
+    const dim3 grid(xcd_grid(Lv.ntg * nqb * nch));
+#define TROWS(NS_)                                                                                               \
+  hipLaunchKernelGGL((k_translate_rows<TF, NS_>), grid, dim3(64 * TG_Q), 0, st, Lv, (const cx<TF>*)S,          \
+                     (const cx<TF>*)T, (cx<TF>*)Gout, Q, R, nqb, cols)
+    if (ns <= 2) TROWS(2); else if (ns == 3) TROWS(3); else if (ns == 4) TROWS(4); else TROWS(5);
+#undef TROWS
     return hipGetLastError();
   }
   const int width = translate_width(Q), ns = translate_split(Q);

@@ -55,7 +55,8 @@ struct pie_op {
   // scalar operator (NT), each stored as its upper triangle
   pie::DevNear NJ{}, NT{};
   void *dNearJ = nullptr, *dNearT = nullptr;
-  int64_t near_entries = 0, near_stored_J = 0, near_stored_T = 0, nslots_J = 0, nslots_T = 0;
+  int64_t near_entries = 0, near_entries_J = 0, near_entries_T = 0;
+  int64_t near_stored_J = 0, near_stored_T = 0, nslots_J = 0, nslots_T = 0;
   int32_t *dPermJ = nullptr, *dPermT = nullptr;  // RWG / triangle slots -> canonical RWG / triangle
   int32_t* dBoxPtr = nullptr;                    // [nbL+1] box-order unknown ranges
   pie::DevTriDiv TD{};                           // divergence sources of the triangles
@@ -441,6 +442,8 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
       return s;
   }
   op->near_entries = entJ + entT;
+  op->near_entries_J = entJ;
+  op->near_entries_T = entT;
   // divergence sources of every triangle (canonical): the RWG functions on
   // its edges with +-l/A (the same value as the box-order divergences)
   {
@@ -618,47 +621,46 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     dl.nug = nug;
     dl.ug_ptr = dug;
     {
-      // sibling groups: runs of boxes with one parent (children are
-      // contiguous in Morton order), the ascending union of their sources,
-      // and each box's entries reordered by union index
-      std::vector<int32_t> sg{0}, su{0}, usrc, seu(lvh.il_src.size()), seo(lvh.il_src.size());
-      bool ok = true;
-      for (int b = 1; b <= nb; ++b)
-        if (b == nb || lvh.parent[b] != lvh.parent[b - 1]) sg.push_back(b);
-      for (size_t g = 0; g + 1 < sg.size(); ++g) {
-        std::vector<int32_t> un;
-        for (int b = sg[g]; b < sg[g + 1]; ++b)
-          for (int64_t e = lvh.il_ptr[b]; e < lvh.il_ptr[b + 1]; ++e) un.push_back((int32_t)lvh.il_src[e]);
-        std::sort(un.begin(), un.end());
-        un.erase(std::unique(un.begin(), un.end()), un.end());
-        ok = ok && un.size() <= (size_t)TB_UMAX && sg[g + 1] - sg[g] <= 8;
-        for (int b = sg[g]; b < sg[g + 1]; ++b) {
-          const int64_t e0 = lvh.il_ptr[b], e1 = lvh.il_ptr[b + 1];
-          ok = ok && e1 - e0 <= (int64_t)TB_SPLIT * TB_EMAX;
-          std::vector<std::pair<int32_t, int32_t>> ent;
-          for (int64_t e = e0; e < e1; ++e)
-            ent.push_back({(int32_t)(std::lower_bound(un.begin(), un.end(), (int32_t)lvh.il_src[e]) - un.begin()),
-                           (int32_t)lvh.il_off[e]});
-          std::sort(ent.begin(), ent.end());
-          for (size_t i = 0; i < ent.size(); ++i) {
-            seu[e0 + i] = ent[i].first;
-            seo[e0 + i] = ent[i].second;
-          }
+      // translation groups: runs of boxes with one parent (children are
+      // contiguous in Morton order) cut into near-equal parts of at most
+      // TG_BOXES boxes; per group the ascending union of its sources, each
+      // with the offset index of every box that lists it
+      std::vector<int32_t> tg{0}, tgent{0};
+      std::vector<int4> te;
+      auto add_group = [&](int b0, int b1) {
+        std::vector<std::pair<int32_t, int32_t>> ent;  // (source, box slot << 16 | offset)
+        for (int b = b0; b < b1; ++b)
+          for (int64_t e = lvh.il_ptr[b]; e < lvh.il_ptr[b + 1]; ++e)
+            ent.push_back({(int32_t)lvh.il_src[e], ((b - b0) << 16) | (int32_t)lvh.il_off[e]});
+        std::sort(ent.begin(), ent.end());
+        for (size_t i = 0; i < ent.size();) {
+          uint32_t o[TG_BOXES];
+          for (int d = 0; d < TG_BOXES; ++d) o[d] = 0xffffu;
+          const int32_t u = ent[i].first;
+          for (; i < ent.size() && ent[i].first == u; ++i) o[ent[i].second >> 16] = ent[i].second & 0xffff;
+          te.push_back(make_int4(u, (int32_t)(o[0] | (o[1] << 16)), (int32_t)(o[2] | (o[3] << 16)), 0));
         }
-        usrc.insert(usrc.end(), un.begin(), un.end());
-        su.push_back((int32_t)usrc.size());
+        tg.push_back(b1);
+        tgent.push_back((int32_t)te.size());
+      };
+      for (int b0 = 0; b0 < nb;) {
+        int b1 = b0 + 1;
+        while (b1 < nb && lvh.parent[b1] == lvh.parent[b0]) ++b1;
+        const int n = b1 - b0, parts = (n + TG_BOXES - 1) / TG_BOXES;
+        for (int p = 0, s0 = b0; p < parts; ++p) {
+          const int s1 = s0 + (n - (s0 - b0) + (parts - p) - 1) / (parts - p);
+          add_group(s0, s1);
+          s0 = s1;
+        }
+        b0 = b1;
       }
-      int32_t *dsg, *dsu, *dusrc, *dseu, *dseo;
-      if ((s = upload(op, &dsg, sg)) || (s = upload(op, &dsu, su)) || (s = upload(op, &dusrc, usrc)) ||
-          (s = upload(op, &dseu, seu)) || (s = upload(op, &dseo, seo)))
-        return s;
-      dl.nsg = (int32_t)sg.size() - 1;
-      dl.sg_ptr = dsg;
-      dl.su_ptr = dsu;
-      dl.su_src = dusrc;
-      dl.se_u = dseu;
-      dl.se_off = dseo;
-      dl.sib_ok = ok;
+      int32_t *dtg, *dtge;
+      int4* dte;
+      if ((s = upload(op, &dtg, tg)) || (s = upload(op, &dtge, tgent)) || (s = upload(op, &dte, te))) return s;
+      dl.ntg = (int32_t)tg.size() - 1;
+      dl.tg_box = dtg;
+      dl.tg_ent = dtge;
+      dl.te = dte;
     }
     op->lv[l] = dl;
     op->il_pairs += (int64_t)lvh.il_src.size();
@@ -1313,6 +1315,8 @@ pie_status pie_operator_info(const pie_op* op, int32_t what, int64_t* value) {
     case PIE_OI_IL_PAIRS: *value = op->il_pairs; break;
     case PIE_OI_INCIDENCES: *value = op->ninc; break;
     case PIE_OI_DEVICE_BYTES: *value = (int64_t)op->bytes; break;
+    case PIE_OI_NEAR_ENTRIES_RWG: *value = op->near_entries_J; break;
+    case PIE_OI_NEAR_ENTRIES_TRI: *value = op->near_entries_T; break;
     default:
       pie::set_error("unknown operator query");
       return PIE_ERR_ARG;

@@ -123,9 +123,17 @@ def test_gradient_workload_finite_differences():
     translation adds only ~1e-11 of rounding (tau = 4, x = 0.15; solves to
     1e-10, so differences carry ~5e-5 of noise at h = 1e-6), to 2e-4 at
     both steps: it tests the adjoint pipeline against its own forward
-    pipeline.  The default operator (tau = 7, x = 0.08, solve floor ~6e-6)
-    is checked at h = 1e-2 to 1e-3; its gradient against the dense oracle is
-    in test_gpu_lowfreq.py.  At 1e-4 wavelength the system's conditioning
+    pipeline.  The default operator (tau = 7, x = 0.08) solves this system
+    only to ~6e-6 (forward) and ~2e-5 (adjoint) in the equilibrated norm, so
+    its solves stop at 5e-5 and it is checked at h = 1 (L is exactly
+    quadratic in a, so the step adds no truncation error; the two losses
+    differ by ~13% of L).  At this conditioning (~1/(k h) ~ 1e5) a solve
+    stopped at 5e-5 leaves ~1% error in the loss and the gradient (measured:
+    1.1% against the tau = 4 gradient, 1.3% against its own differences), so
+    both are asserted to 3e-2: this case checks that the default operator's
+    adjoint pipeline is the gradient of its forward pipeline at that level,
+    not the gradient's accuracy, which the tau = 4 case and the dense-oracle
+    gradient in test_gpu_lowfreq.py carry.  At 1e-4 wavelength the system's conditioning
     (~1/(k h)) makes GMRES slow: the solves take thousands of iterations."""
     from paper_1806_04164_amd import autograd as ag
     w = synth.WORKLOADS["sphere_s5_1e-4lam_r16"]
@@ -142,7 +150,7 @@ def test_gradient_workload_finite_differences():
             ("tau4", pie.Operator(m, tr, w.freq, near_prec=PIE_FP64, far_prec=PIE_FP64, tau=4, x=0.15, max_rhs=R),
              dict(tol=1e-10, restart=300, maxit=6000, refine=4), ((1e-6, 2e-4), (1e-2, 2e-4))),
             ("default", pie.Operator(m, tr, w.freq, near_prec=PIE_FP64, far_prec=PIE_FP64, max_rhs=R),
-             dict(tol=1e-5, restart=300, maxit=6000, refine=2), ((1e-2, 1e-3),))):
+             dict(tol=5e-5, restart=300, maxit=6000, refine=2), ((1.0, 3e-2),))):
 
         def loss(a_np, grad=False):
             a = torch.tensor(a_np, dtype=torch.complex128, device="cuda", requires_grad=grad)
@@ -162,6 +170,11 @@ def test_gradient_workload_finite_differences():
         L0, g = loss(a0, grad=True)
         print(name, "solves", ag.PieSolve.last_info, flush=True)
         dd = float(np.real(np.vdot(g, d)))  # PyTorch convention: dL = Re(conj(g) . da)
+        if name == "tau4":
+            dd_ref = dd
+        else:
+            print(name, "grad.d vs tau4", abs(dd - dd_ref) / abs(dd_ref), flush=True)
+            assert abs(dd - dd_ref) <= 3e-2 * abs(dd_ref)
         for h, tol in steps:
             fd = (loss(a0 + h * d) - loss(a0 - h * d)) / (2 * h)
             rel = abs(fd - dd) / abs(dd)

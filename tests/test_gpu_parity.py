@@ -402,8 +402,8 @@ def test_matrix_core_kernels_against_oracle(s4, R):
     the vector kernels: with PIE_OPT_MATRIX_SHIFTS the FP64 inter-level
     shifts run on the matrix cores (k_mshift_up / k_mshift_down) at every
     level, and with R = 16 columns the pass also takes the batched
-    aggregation and reception (k_maggregate / k_mreceive), the sibling-group
-    translation (k_translate_batch).
+    aggregation and reception (k_maggregate / k_mreceive) and the grouped
+    row translation (k_translate_rows).
     tau = 4, x = 0.15 (round-off amplification ~1e5): every column against
     the oracle's MLFMA to 1e-9 per block, and against the vector-shift
     operator to rounding."""

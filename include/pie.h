@@ -84,6 +84,25 @@ int32_t pie_version(void);
 pie_status pie_mesh_create(const double* V, int64_t nv, const int32_t* T,
                            int64_t nt, pie_mesh** out);
 void pie_mesh_destroy(pie_mesh* m);
+/* Section 4 (the sphere experiments): a closed sphere of the given radius
+ * (metres) meshed as an icosphere with 20 * 4^subdiv triangles and
+ * 10 * 4^subdiv + 2 vertices.  The 12 icosahedron vertices (0, a, b),
+ * (a, b, 0), (b, 0, a) for a = -1, 1 and b = -g, g (g the golden ratio) are
+ * put on the unit sphere; each subdivision splits every triangle into four
+ * (v0 m01 m20, v1 m12 m01, v2 m20 m12, m01 m12 m20), a midpoint vertex
+ * (0.5 (a + b) normalised) being appended when its edge is first met in
+ * face order (edges v0v1, v1v2, v2v0); then vertices are scaled by radius.
+ * jitter > 0 moves vertex v by jitter * h_v * (2u - 1) in each coordinate,
+ * h_v its shortest edge, u the draw 3v + c (coordinate c) of SplitMix64
+ * started at seed, top 53 bits scaled to [0, 1).  The arithmetic is
+ * reproducible bit for bit (no contraction).  Then as pie_mesh_create.
+ * PIE_ERR_ARG unless 0 <= subdiv <= 10, radius > 0, 0 <= jitter < 0.5. */
+pie_status pie_mesh_icosphere(int32_t subdiv, double radius, double jitter,
+                              uint64_t seed, pie_mesh** out);
+/* Vertex and triangle counts, and (if non-NULL) host copies of the mesh's
+ * double [nv][3] vertices and int32 [nt][3] triangles. */
+pie_status pie_mesh_geometry(const pie_mesh* m, int64_t* nv, int64_t* nt,
+                             double* V, int32_t* T);
 /* nE: number of RWG functions, nT: number of triangles (pulses). */
 pie_status pie_mesh_sizes(const pie_mesh* m, int64_t* nE, int64_t* nT);
 /* Host int32 [nE][2] arrays (any may be NULL): edge vertices (a, b),
@@ -309,6 +328,27 @@ pie_status pie_graph_create_batch(pie_op* const* ops, int32_t nobj,
                                   const int64_t* Rs, int32_t adjoint,
                                   pie_graph** out);
 void pie_graph_destroy(pie_graph* g);
+
+/* --------------------------------------------------------- uneven batch --
+ * Uneven batch (the sphere sweep of Section 4 as one workload: objects of
+ * different sizes, frequencies, precisions and RHS counts): the MVMs
+ * y_i = Z_i x_i (or the adjoint products) of several distinct operators in
+ * one call.  pie_batch_create keeps one stream and event per object
+ * (default priority); pie_batch_matvec forks them from `stream`, runs object
+ * i's MVM on its own stream (its schedule's side streams as in pie_matvec)
+ * so that the objects' kernels run concurrently, and joins them back into
+ * `stream` before returning (asynchronous with respect to the host).  xs[i],
+ * ys[i]: device complex128 [N_i][Rs[i]], as for pie_matvec; each result
+ * equals that object's own pie_matvec bit for bit.  PIE_ERR_ARG on null
+ * arguments, an operator given twice, a bad R or stage profiling on.  The
+ * batch holds the operator handles, not ownership; destroy it before them.
+ * Calls on one batch must not overlap. */
+typedef struct pie_batch pie_batch;
+pie_status pie_batch_create(pie_op* const* ops, int32_t nobj, pie_batch** out);
+pie_status pie_batch_matvec(pie_batch* b, const void* const* xs,
+                            void* const* ys, const int64_t* Rs,
+                            int32_t adjoint, void* stream);
+void pie_batch_destroy(pie_batch* b);
 
 /* ---------------------------------------------------------------- RHS --
  * Plane waves E^inc = amp_r pol_r exp(i k khat_r . r) (E0 = 1 V/m scale).

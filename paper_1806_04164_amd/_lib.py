@@ -39,7 +39,8 @@ OI = dict(N=1, Q=2, TAU=3, NEAR_BLOCKS=4, NEAR_ENTRIES=5, NEAR_BYTES=6, NBOX_FIN
 
 # every function declared in include/pie.h
 EXPORTS = [
-    "pie_last_error", "pie_version", "pie_mesh_create", "pie_mesh_destroy", "pie_mesh_sizes",
+    "pie_last_error", "pie_version", "pie_mesh_create", "pie_mesh_destroy", "pie_mesh_icosphere",
+    "pie_mesh_geometry", "pie_mesh_sizes",
     "pie_mesh_edges", "pie_tree_build", "pie_tree_destroy", "pie_tree_query",
     "pie_options_default", "pie_operator_create", "pie_operator_destroy", "pie_operator_info",
     "pie_operator_level", "pie_matvec", "pie_matvec_near", "pie_matvec_far",
@@ -47,7 +48,7 @@ EXPORTS = [
     "pie_profile_enable", "pie_profile_read", "pie_farfield_adjoint",
     "pie_schedule_get", "pie_schedule_set", "pie_autotune",
     "pie_graph_create", "pie_graph_launch", "pie_graph_destroy", "pie_graph_create_batch",
-    "pie_solve_noalloc",
+    "pie_solve_noalloc", "pie_batch_create", "pie_batch_matvec", "pie_batch_destroy",
 ]
 STAGES = ["permute", "near", "aggregate", "shift_up", "translate", "receive", "shift_down"]
 
@@ -93,6 +94,8 @@ def lib():
         "pie_version": (I32, []),
         "pie_mesh_create": (I32, [P, I64, P, I64, ctypes.POINTER(P)]),
         "pie_mesh_destroy": (None, [P]),
+        "pie_mesh_icosphere": (I32, [I32, D, D, ctypes.c_uint64, ctypes.POINTER(P)]),
+        "pie_mesh_geometry": (I32, [P, pI64, pI64, P, P]),
         "pie_mesh_sizes": (I32, [P, pI64, pI64]),
         "pie_mesh_edges": (I32, [P, P, P, P]),
         "pie_tree_build": (I32, [P, I32, ctypes.POINTER(P)]),
@@ -125,6 +128,9 @@ def lib():
         "pie_graph_create": (I32, [P, P, P, I64, I32, ctypes.POINTER(P)]),
         "pie_graph_launch": (I32, [P, P]),
         "pie_graph_destroy": (None, [P]),
+        "pie_batch_create": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(P)]),
+        "pie_batch_matvec": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), pI64, I32, P]),
+        "pie_batch_destroy": (None, [P]),
         "pie_graph_create_batch": (I32, [ctypes.POINTER(P), I32, ctypes.POINTER(P), ctypes.POINTER(P),
                                          pI64, I32, ctypes.POINTER(P)]),
     }

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <unordered_map>
+#include <limits>
 
 #include "pie_internal.h"
 
@@ -292,6 +294,135 @@ pie_status build_tree(const Mesh& m, int L, Tree& t) {
       lv.il_ptr.push_back((int64_t)lv.il_src.size());
     }
   }
+  return PIE_OK;
+}
+
+
+// ------------------------------------------------------------ icosphere --
+// The sphere meshes of the Section 4 experiments, generated here so that a
+// caller can build a workload without its own mesher.  Built with
+// -ffp-contract=off; every coordinate is formed by the operation sequence
+// written below (norms as ((x*x + y*y) + z*z), midpoints as 0.5 * (a + b)
+// then divided by their norm), so that results are reproducible bit for bit
+// on any IEEE host.
+namespace {
+
+double norm3(double x, double y, double z) { return std::sqrt((x * x + y * y) + z * z); }
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): draw n (n = 0, 1, ...) of
+// the stream started at seed is mix(seed + (n + 1) * gamma).
+uint64_t splitmix(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + (n + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+pie_status icosphere(int subdiv, double radius, double jitter, uint64_t seed, std::vector<double>& V,
+                     std::vector<int32_t>& T) {
+  if (subdiv < 0 || subdiv > 10 || !(radius > 0.0) || !std::isfinite(radius) || !(jitter >= 0.0) ||
+      !(jitter < 0.5)) {
+    set_error("icosphere: need 0 <= subdiv <= 10, radius > 0 and 0 <= jitter < 0.5");
+    return PIE_ERR_ARG;
+  }
+  // the 12 vertices of the regular icosahedron: (0, a, b), (a, b, 0),
+  // (b, 0, a) for a = -1, 1 and b = -g, g (g the golden ratio), on the unit
+  // sphere
+  const double g = (1.0 + std::pow(5.0, 0.5)) / 2.0;
+  V.clear();
+  for (double a : {-1.0, 1.0})
+    for (double b : {-g, g}) {
+      const double p[3][3] = {{0.0, a, b}, {a, b, 0.0}, {b, 0.0, a}};
+      for (const auto& q : p) {
+        const double n = norm3(q[0], q[1], q[2]);
+        V.insert(V.end(), {q[0] / n, q[1] / n, q[2] / n});
+      }
+    }
+  // faces: triples of mutually adjacent vertices (shortest chord), i < j < k,
+  // oriented counter-clockwise seen from outside
+  auto dist = [&](int i, int j) {
+    return norm3(V[3 * i] - V[3 * j], V[3 * i + 1] - V[3 * j + 1], V[3 * i + 2] - V[3 * j + 2]);
+  };
+  double e = 1e300;
+  for (int i = 0; i < 12; ++i)
+    for (int j = 0; j < 12; ++j)
+      if (i != j) e = std::min(e, dist(i, j));
+  auto adj = [&](int i, int j) { return std::abs(dist(i, j) - e) < 1e-9; };
+  std::vector<int64_t> F;
+  for (int i = 0; i < 12; ++i)
+    for (int j = i + 1; j < 12; ++j) {
+      if (!adj(i, j)) continue;
+      for (int k = j + 1; k < 12; ++k) {
+        if (!adj(i, k) || !adj(j, k)) continue;
+        const double* a = &V[3 * i];
+        const double* b = &V[3 * j];
+        const double* c = &V[3 * k];
+        const double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        const double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+        const double d = n[0] * (a[0] + b[0] + c[0]) + n[1] * (a[1] + b[1] + c[1]) + n[2] * (a[2] + b[2] + c[2]);
+        if (d < 0.0)
+          F.insert(F.end(), {i, k, j});
+        else
+          F.insert(F.end(), {i, j, k});
+      }
+    }
+  if (F.size() != 60) {
+    set_error("icosphere: icosahedron construction failed");
+    return PIE_ERR_MESH;
+  }
+  // subdivision: every face into four; a new vertex (the normalised
+  // midpoint) is appended when an edge is first met, walking the faces in
+  // order and each face's edges v0v1, v1v2, v2v0
+  for (int s = 0; s < subdiv; ++s) {
+    const int64_t nv = (int64_t)V.size() / 3, nf = (int64_t)F.size() / 3;
+    std::unordered_map<int64_t, int64_t> mid;
+    mid.reserve(2 * nf);
+    std::vector<int64_t> NF;
+    NF.reserve(12 * nf);
+    int64_t next = nv;
+    for (int64_t f = 0; f < nf; ++f) {
+      int64_t m[3];
+      for (int k = 0; k < 3; ++k) {
+        const int64_t a = F[3 * f + k], b = F[3 * f + (k + 1) % 3];
+        const int64_t lo = std::min(a, b), hi = std::max(a, b), key = lo * nv + hi;
+        auto it = mid.find(key);
+        if (it == mid.end()) {
+          double p[3];
+          for (int c = 0; c < 3; ++c) p[c] = 0.5 * (V[3 * lo + c] + V[3 * hi + c]);
+          const double n = norm3(p[0], p[1], p[2]);
+          V.insert(V.end(), {p[0] / n, p[1] / n, p[2] / n});
+          it = mid.emplace(key, next++).first;
+        }
+        m[k] = it->second;  // m01, m12, m20
+      }
+      const int64_t v0 = F[3 * f], v1 = F[3 * f + 1], v2 = F[3 * f + 2];
+      NF.insert(NF.end(), {v0, m[0], m[2], v1, m[1], m[0], v2, m[2], m[1], m[0], m[1], m[2]});
+    }
+    F.swap(NF);
+  }
+  for (double& c : V) c = c * radius;
+  if (jitter > 0.0) {
+    // vertex v moves by jitter * h_v * (2 u - 1) per coordinate, h_v the
+    // shortest edge at v, u = draw 3 v + c of SplitMix64(seed) scaled to [0, 1)
+    const int64_t nv = (int64_t)V.size() / 3;
+    std::vector<double> h(nv, std::numeric_limits<double>::infinity());
+    for (size_t f = 0; f < F.size(); f += 3)
+      for (int k = 0; k < 3; ++k) {
+        const int64_t a = F[f + k], b = F[f + (k + 1) % 3];
+        const double L = norm3(V[3 * a] - V[3 * b], V[3 * a + 1] - V[3 * b + 1], V[3 * a + 2] - V[3 * b + 2]);
+        h[a] = std::min(h[a], L);
+        h[b] = std::min(h[b], L);
+      }
+    for (int64_t v = 0; v < nv; ++v)
+      for (int c = 0; c < 3; ++c) {
+        const double u = (double)(splitmix(seed, (uint64_t)(3 * v + c)) >> 11) * 0x1.0p-53;
+        V[3 * v + c] = V[3 * v + c] + (jitter * h[v]) * (2.0 * u - 1.0);
+      }
+  }
+  T.assign(F.begin(), F.end());
   return PIE_OK;
 }
 

@@ -144,6 +144,21 @@ struct pie_graph {
   }
 };
 
+// Uneven batch: one stream and one completion event per object (default
+// priority, non-blocking), forked from and joined back to the caller's
+// stream on every call.
+struct pie_batch {
+  std::vector<pie_op*> ops;
+  std::vector<hipStream_t> st;
+  std::vector<hipEvent_t> done;
+  hipEvent_t start = nullptr;
+  ~pie_batch() {
+    for (hipStream_t s : st) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : done) (void)hipEventDestroy(e);
+    if (start) (void)hipEventDestroy(start);
+  }
+};
+
 namespace {
 
 using namespace pie;
@@ -1116,6 +1131,31 @@ pie_status pie_mesh_create(const double* V, int64_t nv, const int32_t* T, int64_
 }
 void pie_mesh_destroy(pie_mesh* m) { delete m; }
 
+pie_status pie_mesh_icosphere(int32_t subdiv, double radius, double jitter, uint64_t seed, pie_mesh** out) {
+  if (!out) {
+    pie::set_error("null output handle");
+    return PIE_ERR_ARG;
+  }
+  *out = nullptr;
+  std::vector<double> V;
+  std::vector<int32_t> T;
+  pie_status s = pie::icosphere(subdiv, radius, jitter, seed, V, T);
+  if (s) return s;
+  return pie_mesh_create(V.data(), (int64_t)V.size() / 3, T.data(), (int64_t)T.size() / 3, out);
+}
+
+pie_status pie_mesh_geometry(const pie_mesh* m, int64_t* nv, int64_t* nt, double* V, int32_t* T) {
+  if (!m) {
+    pie::set_error("null mesh");
+    return PIE_ERR_ARG;
+  }
+  if (nv) *nv = m->m.nv;
+  if (nt) *nt = m->m.nt;
+  if (V) std::memcpy(V, m->m.V.data(), m->m.V.size() * sizeof(double));
+  if (T) std::memcpy(T, m->m.T.data(), m->m.T.size() * sizeof(int32_t));
+  return PIE_OK;
+}
+
 pie_status pie_mesh_sizes(const pie_mesh* m, int64_t* nE, int64_t* nT) {
   if (!m) {
     pie::set_error("null mesh");
@@ -1515,6 +1555,67 @@ pie_status pie_graph_create_batch(pie_op* const* ops, int32_t nobj, const void* 
   *out = g.release();
   return PIE_OK;
 }
+
+pie_status pie_batch_create(pie_op* const* ops, int32_t nobj, pie_batch** out) {
+  if (!out || !ops || nobj < 1) {
+    pie::set_error("null argument or empty batch");
+    return PIE_ERR_ARG;
+  }
+  *out = nullptr;
+  for (int i = 0; i < nobj; ++i) {
+    if (!ops[i]) {
+      pie::set_error("null operator in the batch");
+      return PIE_ERR_ARG;
+    }
+    for (int j = 0; j < i; ++j)
+      if (ops[j] == ops[i]) {
+        pie::set_error("an operator appears twice in the batch");
+        return PIE_ERR_ARG;
+      }
+  }
+  auto b = std::make_unique<pie_batch>();
+  b->ops.assign(ops, ops + nobj);
+  HIPCHK(hipEventCreateWithFlags(&b->start, hipEventDisableTiming), "batch event");
+  for (int i = 0; i < nobj; ++i) {
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "batch stream");
+    b->st.push_back(s);
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "batch event");
+    b->done.push_back(e);
+  }
+  *out = b.release();
+  return PIE_OK;
+}
+
+pie_status pie_batch_matvec(pie_batch* b, const void* const* xs, void* const* ys, const int64_t* Rs,
+                            int32_t adjoint, void* stream) {
+  if (!b || !xs || !ys || !Rs) {
+    pie::set_error("null argument");
+    return PIE_ERR_ARG;
+  }
+  const int n = (int)b->ops.size();
+  for (int i = 0; i < n; ++i) {
+    pie_status s = check_op_call(b->ops[i], xs[i], ys[i], Rs[i]);
+    if (s) return s;
+    if (b->ops[i]->prof) {
+      pie::set_error("stage profiling must be off for a batch call");
+      return PIE_ERR_ARG;
+    }
+  }
+  hipStream_t cs = (hipStream_t)stream;
+  HIPCHK(hipEventRecord(b->start, cs), "batch fork");
+  for (int i = 0; i < n; ++i) {
+    HIPCHK(hipStreamWaitEvent(b->st[i], b->start, 0), "batch fork");
+    pie_status s = mvm(b->ops[i], xs[i], ys[i], Rs[i], 3 | (adjoint ? 4 : 0), b->st[i]);
+    if (s) return s;
+    HIPCHK(hipEventRecord(b->done[i], b->st[i]), "batch join");
+    HIPCHK(hipStreamWaitEvent(cs, b->done[i], 0), "batch join");
+  }
+  return PIE_OK;
+}
+
+void pie_batch_destroy(pie_batch* b) { delete b; }
 
 pie_status pie_graph_launch(pie_graph* g, void* stream) {
   if (!g || !g->exec) {

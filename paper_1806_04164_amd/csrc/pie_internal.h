@@ -56,6 +56,9 @@ struct Tree {
 
 pie_status build_mesh(const double* V, int64_t nv, const int32_t* T, int64_t nt, Mesh& m);
 pie_status build_tree(const Mesh& m, int L, Tree& t);
+// Icosphere of radius `radius` with 20 * 4^subdiv triangles (host, bit-reproducible).
+pie_status icosphere(int subdiv, double radius, double jitter, uint64_t seed, std::vector<double>& V,
+                     std::vector<int32_t>& T);
 int64_t morton3(int64_t x, int64_t y, int64_t z);
 int offset_id(int64_t dx, int64_t dy, int64_t dz);
 

@@ -36,6 +36,25 @@ class Mesh:
             _destroy(self.h)
             self.h = None
 
+    @classmethod
+    def icosphere(cls, subdiv: int, radius: float, jitter: float = 0.0, seed: int = 0) -> "Mesh":
+        """The library's icosphere generator (pie_mesh_icosphere)."""
+        h = ctypes.c_void_p()
+        check(lib().pie_mesh_icosphere(int(subdiv), float(radius), float(jitter), int(seed), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self.h = h
+        self.V, self.T = self.geometry()
+        return self
+
+    def geometry(self):
+        """(V [nv, 3] float64, T [nt, 3] int32) as held by the library."""
+        nv, nt = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().pie_mesh_geometry(self.h, ctypes.byref(nv), ctypes.byref(nt), None, None))
+        V = np.zeros((nv.value, 3), np.float64)
+        T = np.zeros((nt.value, 3), np.int32)
+        check(lib().pie_mesh_geometry(self.h, None, None, _ptr(V), _ptr(T)))
+        return V, T
+
     def sizes(self):
         ne, nt = ctypes.c_int64(), ctypes.c_int64()
         check(lib().pie_mesh_sizes(self.h, ctypes.byref(ne), ctypes.byref(nt)))
@@ -121,6 +140,45 @@ class Graph:
         return self.y
 
     def __del__(self, _destroy=lib().pie_graph_destroy):
+        # the destroy function is bound at definition time: it stays callable
+        # while the interpreter tears modules down
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
+
+
+class Batch:
+    """pie_batch: the MVMs y_i = Z_i x_i (or Z_i^H x_i) of several distinct
+    operators in one call, each object on its own stream so that their
+    kernels run concurrently.  Keeps the operators alive."""
+
+    def __init__(self, ops):
+        n = len(ops)
+        if n == 0:
+            raise ValueError("empty batch")
+        self.ops = list(ops)
+        P = ctypes.c_void_p
+        hops = (P * n)(*[op.h.value for op in ops])
+        h = P()
+        check(lib().pie_batch_create(hops, n, ctypes.byref(h)))
+        self.h = h
+
+    def matvec(self, xs, ys=None, adjoint=False, stream=None):
+        import torch
+        n = len(self.ops)
+        if len(xs) != n or (ys is not None and len(ys) != n):
+            raise ValueError("one x (and y) per operator")
+        if ys is None:
+            ys = [torch.empty_like(x) for x in xs]
+        P = ctypes.c_void_p
+        Rs = [op._R(x) for op, x in zip(self.ops, xs)]
+        hx = (P * n)(*[_dev(x, op.N).value for op, x in zip(self.ops, xs)])
+        hy = (P * n)(*[_dev(y, op.N, R).value for op, y, R in zip(self.ops, ys, Rs)])
+        hr = (ctypes.c_int64 * n)(*Rs)
+        check(lib().pie_batch_matvec(self.h, hx, hy, hr, int(adjoint), _stream(stream)))
+        return ys
+
+    def __del__(self, _destroy=lib().pie_batch_destroy):
         # the destroy function is bound at definition time: it stays callable
         # while the interpreter tears modules down
         if getattr(self, "h", None):

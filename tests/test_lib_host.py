@@ -62,6 +62,29 @@ def test_tree_bit_exact(s, L, jit):
             assert np.array_equal(tr.query("IL_OFF", l), ot.levels[l].il_off)
 
 
+@pytest.mark.parametrize("s,jit,seed", [(0, 0.0, 0), (1, 0.0, 0), (3, 0.0, 0), (4, 0.05, 2), (5, 0.05, 2),
+                                        (6, 0.0, 0), (2, 0.3, 123456789012345)])
+def test_icosphere_bit_exact(s, jit, seed):
+    """pie_mesh_icosphere (C++) against the workloads' generator: vertices
+    and triangles equal bit for bit, so a mesh built by the library is the
+    workload's mesh (the jittered ones included)."""
+    m = pie.Mesh.icosphere(s, synth.DIAMETER / 2, jit, seed)
+    V, T = synth.icosphere(s, synth.DIAMETER / 2, jit, seed)
+    assert m.V.shape == (10 * 4 ** s + 2, 3) and m.T.shape == (20 * 4 ** s, 3)
+    assert np.array_equal(m.V, V)
+    assert np.array_equal(m.T, T)
+    om = omesh.build(V, T)
+    assert m.sizes() == (om.nE, om.nT)
+
+
+def test_icosphere_errors():
+    for args in ((-1, 0.3, 0.0, 0), (11, 0.3, 0.0, 0), (2, 0.0, 0.0, 0), (2, float("nan"), 0.0, 0),
+                 (2, 0.3, -0.1, 0), (2, 0.3, 0.5, 0)):
+        with pytest.raises(_lib.PieError) as ei:
+            pie.Mesh.icosphere(*args)
+        assert ei.value.status == _lib.PIE_ERR_ARG
+
+
 def test_mesh_errors():
     V, T = synth.icosphere(1)
     bad = T.copy()

@@ -230,7 +230,7 @@ pie_status pie_operator_level(const pie_op* op, int32_t level, double* s,
  * two conjugations into its input and output kernels.
  * Columns are processed in passes of at most min(max_rhs, 64).  Passes of 16
  * or more columns run batched kernels (matrix-core near field, aggregation,
- * shifts and reception; sibling-group translation), narrower passes the
+ * shifts and reception; grouped row translation), narrower passes the
  * single-column kernels.  A column's result is bitwise the same for every
  * pass width on the same side of that boundary; across it the summation
  * order differs (FP64 rounding, amplified by the sampled translation). */

@@ -132,7 +132,7 @@ struct pie_op {
 // wider batches run in several passes.
 constexpr int kPassMax = 64;
 // Passes of at least this many columns run the batched (matrix-core and
-// sibling-group) kernels.
+// grouped row translation) kernels.
 constexpr int kBatchCols = 16;
 
 struct pie_graph {

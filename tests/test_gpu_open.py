@@ -187,11 +187,13 @@ def test_patch_adjoint_against_dense(p16):
 def test_paper_patch_batched_passes(p75):
     """16 right-hand sides of the paper's patch in one pass: the batched
     kernels (matrix-core near field, aggregation, reception and shifts,
-    sibling-group translation) on a flat scatterer whose boxes lie on box
+    grouped row translation) on a flat scatterer whose boxes lie on box
     faces.  A column equals itself bit for bit in any pass of >= 16
     columns, matches its single-column MVM to the FP64 rounding carried
     through the translations (< 2e-4, as on the sphere), and its sampled
-    oracle rows to 1e-3."""
+    oracle rows to 1e-3 per sub-operator (rows J/A x input J/A: the blocks'
+    scales differ by ~1e6, so a summed comparison would hide the small
+    ones)."""
     f = 1e8
     R = 16
     op = pie.Operator(p75["mesh"], p75["trees"][5], f, near_prec=PIE_FP32, far_prec=PIE_FP64, max_rhs=20)
@@ -208,8 +210,12 @@ def test_paper_patch_batched_passes(p75):
     rng = np.random.default_rng(12)
     rows = np.sort(np.concatenate([rng.choice(E, 4, replace=False), E + rng.choice(N - E, 4, replace=False)]))
     ref = sampled_rows([(("patch", 75), f, rows, 91, 20)])[0]
-    yr = y20[rows]
-    full = ref["J"] + ref["A"]
-    err = np.linalg.norm(yr - full) / np.linalg.norm(full)
-    print("patch 75 batched vs oracle rows", err, flush=True)
-    assert err <= 1e-3
+    errs = {}
+    for name, sl in (("J", slice(0, E)), ("A", slice(E, None))):
+        xm = np.zeros_like(x)
+        xm[sl] = x[sl]
+        yr = host(op.matvec(dev(xm)))[rows]
+        for rn, rs in (("J", rows < E), ("A", rows >= E)):
+            errs[rn + name] = np.linalg.norm(yr[rs] - ref[name][rs]) / np.linalg.norm(ref[name][rs])
+    print("patch 75 batched vs oracle rows", errs, flush=True)
+    assert max(errs.values()) <= 1e-3

@@ -200,7 +200,7 @@ def test_batched_aggregation(c1):
 
 
 def test_fp32_operator_batched(c1):
-    """The FP32 operator in a batched pass (sibling-group translation in
+    """The FP32 operator in a batched pass (grouped row translation in
     FP32, FP32 matrix-core near field): a column against the oracle's
     MLFMA with the same tau and x, as for one column."""
     R = 20

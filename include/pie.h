@@ -147,10 +147,20 @@ pie_status pie_tree_query(const pie_tree* t, int32_t what, int32_t level,
  * precision to values chosen by measured error against the dense matrix
  * (sampled rows, 4 to 8 levels) and by the rounding that the sampled
  * translation amplifies by about (2 tau + 1)!!/(2 x)^tau:
- *   far FP64: tau = 7 (Q = 128), x = 0.08 for trees of up to 5 levels,
- *             0.07 for 6 and 0.06 for 7 or more (deeper trees accumulate
- *             more of the inter-level rescaling error, which grows as x^2);
- *   far FP32: tau = 4, x = 0.15.
+ *   far FP64: x = 0.08 for trees of up to 5 levels, 0.07 for 6 and 0.06
+ *             for 7 or more (deeper trees accumulate more of the inter-level
+ *             rescaling error, which grows as x^2); the truncation number
+ *             per level from its box size: tau_l = 7 for k d_l <= 0.8, 8 for
+ *             <= 1.6, 9 for <= 3.2, 10 for <= 4.8 (Section 3: as boxes grow, s -> 1 and
+ *             Eq. (5) becomes the ordinary translation function, which
+ *             needs more terms; measured against sampled dense rows at 1 to
+ *             3 wavelengths); PIE_ERR_UNSUPPORTED for larger level-3 boxes;
+ *   far FP32: tau = 4, x = 0.15, k d_3 <= 1.
+ * A caller's tau (> 0) applies at every level and covers k d_l up to 1.0
+ * (tau < 7), 1.6 (7, 8), 3.2 (9) or 4.8 (>= 10).  Every level uses the
+ * k-space samples of the largest tau_l (so no interpolation between
+ * levels); the inter-level filter keeps degrees up to the parent level's
+ * tau_l.
  * Near/far split (Section 3 does not state it): Z^JA = G S, Z^AJ = S G^T and
  * Z^AA = w^2 eps0 S share the scalar operator S_qp = <P_q, int P_p g> (G: the
  * RWG divergence per triangle).  S is applied per triangle -- each triangle's
@@ -162,7 +172,7 @@ pie_status pie_tree_query(const pie_tree* t, int32_t what, int32_t level,
  * charge null vector of the dense matrix, which keeps low-frequency solves
  * as accurate as the operator.
  * k-space samples: n_theta Gauss-Legendre points in cos(theta) (default
- * tau+1) times n_phi uniform phi (default 2 tau + 2).
+ * tau+1, tau the largest tau_l) times n_phi uniform phi (default 2 tau + 2).
  * near_prec: storage and arithmetic of the near-field SpMM.
  * far_prec: patterns, translation and shifts.
  * Tables (translation, filters) are always computed in FP64. */
@@ -170,7 +180,7 @@ typedef struct pie_options {
   int32_t version;   /* must be 1                                      */
   int32_t near_prec; /* PIE_FP32 or PIE_FP64                           */
   int32_t far_prec;  /* PIE_FP32 or PIE_FP64                           */
-  int32_t tau;       /* 0: default for far_prec                        */
+  int32_t tau;       /* 0: default for far_prec (per level, above)     */
   double x;          /* 0: default for far_prec                        */
   int32_t n_theta;   /* 0: tau + 1                                     */
   int32_t n_phi;     /* 0: 2 tau + 2                                   */
@@ -204,7 +214,7 @@ void pie_operator_destroy(pie_op* op);
 
 #define PIE_OI_N 1          /* number of unknowns                         */
 #define PIE_OI_Q 2          /* k-space samples per level                  */
-#define PIE_OI_TAU 3
+#define PIE_OI_TAU 3        /* largest truncation number over the levels  */
 #define PIE_OI_NEAR_BLOCKS 4 /* stored (upper-triangle) near blocks       */
 #define PIE_OI_NEAR_ENTRIES 5 /* stored near-field entries                */
 #define PIE_OI_NEAR_BYTES 6  /* bytes of stored near-field entries        */
@@ -216,6 +226,8 @@ void pie_operator_destroy(pie_op* op);
 #define PIE_OI_NEAR_ENTRIES_TRI 12 /* stored triangle-triangle entries of  */
                                    /* the scalar operator (applied to x_A  */
                                    /* and u)                               */
+/* truncation number of Eq. (5) at level l (3..L) */
+#define PIE_OI_TAU_LEVEL(l) (100 + (l))
 pie_status pie_operator_info(const pie_op* op, int32_t what, int64_t* value);
 /* Scale factor s and kappa = k/s at level l (3..L). */
 pie_status pie_operator_level(const pie_op* op, int32_t level, double* s,

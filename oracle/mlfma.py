@@ -32,6 +32,12 @@ Readings where the paper is silent:
 * scale factor per level: s_l = min(1, k d_l / x), so kappa_l d_l = x (the
   scaled box size) wherever s < 1.  The tables of tau and s of the paper's
   reference [jp045] are not available; (tau, x) are chosen by measured error.
+* truncation per level: as boxes grow, s -> 1 and Eq. (5) becomes the
+  ordinary translation function, which needs more terms; a level may take
+  its own tau_l (Params.level_tau), while every level keeps the k-space
+  samples of the largest tau (so patterns move between levels without
+  interpolation) and the inter-level filter keeps degrees up to the parent
+  level's tau_l.
 * shifting a pattern from a child (kappa_c) to its parent (kappa_p): the
   degree-l spherical-harmonic content is rescaled by (kappa_p/kappa_c)^l
   (the same small-argument behaviour s^t j_t(k v/s) ~ j_t(k v) that underlies
@@ -60,10 +66,14 @@ from . import octree as _octree
 
 @dataclasses.dataclass(frozen=True)
 class Params:
-    tau: int = 6          # truncation number of Eq. (5)
+    tau: int = 6          # truncation number of Eq. (5) (the largest, when per level)
     x: float = 0.07       # scaled box size k d / s where s < 1
     n_theta: int = 0      # 0: tau + 1
     n_phi: int = 0        # 0: 2 tau + 2
+    level_tau: tuple = ()  # ((level, tau_l), ...): a smaller truncation at those levels
+
+    def tau_at(self, level):
+        return dict(self.level_tau).get(level, self.tau)
 
     @property
     def nth(self):
@@ -167,11 +177,11 @@ class MLFMA:
         for l in range(3, L + 1):
             tab = np.zeros((offs.shape[0], self.Q), dtype=np.complex128)
             for i, o in enumerate(offs):
-                tab[i] = pref * self.w * alpha_tilde(k, self.s[l], params.tau, o * self.d[l], self.khat)
+                tab[i] = pref * self.w * alpha_tilde(k, self.s[l], params.tau_at(l), o * self.d[l], self.khat)
             self.T[l] = tab
         self.F = {}
         for l in range(3, L):
-            self.F[l] = interlevel_filter(self.khat, self.w, params.tau,
+            self.F[l] = interlevel_filter(self.khat, self.w, params.tau_at(l),
                                           self.kappa[l] / self.kappa[l + 1])
         m = prob.mesh
         self.E = m.nE

@@ -82,6 +82,7 @@ struct pie_op {
   // levels (index l)
   std::vector<pie::DevLevel> lv;
   std::vector<double> s_l, kappa_l, d_l;
+  std::vector<int> tau_l;  // truncation of Eq. (5) per level (>= 3)
   int64_t il_pairs = 0;
   // tables in far precision
   void* dM = nullptr;  // per-incidence moments [ninc][Qh][4] in far precision
@@ -681,7 +682,7 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     op->il_pairs += (int64_t)lvh.il_src.size();
   }
   // ---------------- k-space samples and tables (FP64)
-  const int Q = op->Q, tau = op->tau;
+  const int Q = op->Q;
   std::vector<double> ct, wt;
   gauss_legendre(op->nth, ct, wt);
   std::vector<double> khat(3 * (size_t)Q), wq(Q);
@@ -708,13 +709,13 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
           double wv[3] = {a * op->d_l[l], b * op->d_l[l], c * op->d_l[l]};
           double wn = std::sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
           std::vector<double> hk;
-          scaled_hankel(op->k, op->s_l[l], wn, tau, hk);  // k s^t h_t
+          scaled_hankel(op->k, op->s_l[l], wn, op->tau_l[l], hk);  // k s^t h_t
           for (int q = 0; q < Q; ++q) {
             double x = (khat[3 * q] * wv[0] + khat[3 * q + 1] * wv[1] + khat[3 * q + 2] * wv[2]) / wn;
             std::complex<double> acc(0.0, 0.0);
             double p0 = 1.0, p1 = x;
             std::complex<double> it(1.0, 0.0);  // i^t
-            for (int tt = 0; tt <= tau; ++tt) {
+            for (int tt = 0; tt <= op->tau_l[l]; ++tt) {
               double Pt = tt == 0 ? 1.0 : (tt == 1 ? x : 0.0);
               if (tt >= 2) {
                 double p2 = ((2.0 * tt - 1.0) * x * p1 - (tt - 1.0) * p0) / tt;
@@ -733,7 +734,8 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
           ++id;
         }
     if (l < L) {
-      // inter-level filter F[q][q'] = w_q' sum_l (2l+1)/4pi ratio^l P_l(khat_q.khat_q')
+      // inter-level filter F[q][q'] = w_q' sum_l (2l+1)/4pi ratio^l P_l(khat_q.khat_q'),
+      // degrees up to the parent level's truncation
       const double ratio = op->kappa_l[l] / op->kappa_l[l + 1];
       Ft[l].assign((size_t)Q * Q, 0.0);
       for (int q = 0; q < Q; ++q)
@@ -741,7 +743,7 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
           double x = khat[3 * q] * khat[3 * qq] + khat[3 * q + 1] * khat[3 * qq + 1] + khat[3 * q + 2] * khat[3 * qq + 2];
           x = std::max(-1.0, std::min(1.0, x));
           double p0 = 1.0, p1 = x, sum = 1.0 / (4.0 * kPi), rp = 1.0;
-          for (int ll = 1; ll <= tau; ++ll) {
+          for (int ll = 1; ll <= op->tau_l[l]; ++ll) {
             double Pl;
             if (ll == 1) {
               Pl = x;
@@ -1282,13 +1284,32 @@ pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq
   op->near_prec = opt->near_prec;
   op->far_prec = opt->far_prec;
   const bool f32 = opt->far_prec == PIE_FP32;
-  op->tau = opt->tau > 0 ? opt->tau : (f32 ? 4 : 7);
   // FP64 far field: x = 0.08 keeps the translation's rounding nonlinearity
   // near 4e-6; deeper trees accumulate more of the inter-level rescaling
   // error (proportional to x^2), so 6 levels take 0.07 and 7 or more 0.06
   // (nonlinearity 1e-5 and 3e-5)
   const int Lt = t->t.L;
   op->xs = opt->x > 0.0 ? opt->x : (f32 ? 0.15 : (Lt <= 5 ? 0.08 : (Lt == 6 ? 0.07 : 0.06)));
+  // truncation number of Eq. (5) per level from the level's box size k d_l:
+  // tau = 7 up to k d = 0.8, 8 up to 1.6, 9 up to 3.2, 10 up to 4.8 (FP64
+  // default; measured against sampled dense rows at 1 to 3 wavelengths), or
+  // the caller's tau at every level; the k-space samples are those of the
+  // largest tau, at every level
+  op->tau_l.assign(Lt + 1, 0);
+  int tmax = 0;
+  for (int l = 3; l <= Lt; ++l) {
+    const double kd = op->k * t->t.side / (double)(int64_t(1) << (l - 1));
+    const int tl = opt->tau > 0 ? opt->tau : (f32 ? 4 : (kd <= 0.8 ? 7 : (kd <= 1.6 ? 8 : (kd <= 3.2 ? 9 : 10))));
+    const double kdmax = f32 || tl < 7 ? 1.0 : (tl < 9 ? 1.6 : (tl < 10 ? 3.2 : 4.8));
+    if (kd > kdmax) {
+      pie::set_error("level-" + std::to_string(l) + " boxes (k d = " + std::to_string(kd) +
+                     ") exceed what the truncation number covers: use more levels, or the FP64 far field");
+      return PIE_ERR_UNSUPPORTED;
+    }
+    op->tau_l[l] = tl;
+    tmax = std::max(tmax, tl);
+  }
+  op->tau = tmax;
   op->nth = opt->n_theta > 0 ? opt->n_theta : op->tau + 1;
   op->nph = opt->n_phi > 0 ? opt->n_phi : 2 * op->tau + 2;
   op->Q = op->nth * op->nph;
@@ -1302,14 +1323,13 @@ pie_status pie_operator_create(const pie_mesh* m, const pie_tree* t, double freq
     pie::set_error("tau <= 20, Q <= 1024 and an even n_phi are required");
     return PIE_ERR_ARG;
   }
-  const double d3 = t->t.side / 4.0;
-  if (op->k * d3 > 1.0) {
-    pie::set_error("level-3 boxes exceed 1/(2 pi) wavelengths: outside the low-frequency regime");
-    return PIE_ERR_UNSUPPORTED;
+  // round-off amplification of the sampled translation at level l:
+  // (2 tau_l + 1)!!/(2 x_l)^tau_l with x_l = k d_l / s_l = max(k d_l, x)
+  double amp = 0.0;
+  for (int l = 3; l <= Lt; ++l) {
+    const double kd = op->k * t->t.side / (double)(int64_t(1) << (l - 1));
+    amp = std::max(amp, dfact(2 * op->tau_l[l] + 1) / std::pow(2.0 * std::max(kd, op->xs), op->tau_l[l]));
   }
-  // round-off amplification of the sampled translation: (2 tau + 1)!!/(2 x)^tau
-  const double xe = std::min(op->xs, op->k * d3);
-  const double amp = dfact(2 * op->tau + 1) / std::pow(2.0 * std::max(xe, op->xs), op->tau);
   const double eps = f32 ? 5.96e-8 : 1.11e-16;
   if (eps * amp > 1e-2) {
     pie::set_error("tau and x amplify round-off beyond 1e-2 in this far-field precision");
@@ -1358,6 +1378,10 @@ pie_status pie_operator_info(const pie_op* op, int32_t what, int64_t* value) {
     case PIE_OI_NEAR_ENTRIES_RWG: *value = op->near_entries_J; break;
     case PIE_OI_NEAR_ENTRIES_TRI: *value = op->near_entries_T; break;
     default:
+      if (what >= PIE_OI_TAU_LEVEL(3) && what <= PIE_OI_TAU_LEVEL(op->L)) {
+        *value = op->tau_l[what - PIE_OI_TAU_LEVEL(0)];
+        break;
+      }
       pie::set_error("unknown operator query");
       return PIE_ERR_ARG;
   }

@@ -46,7 +46,10 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 // k -> 0 with s proportional to k:
 //   u_{t+1} = (2t+1)(s/z) u_t - s^2 u_{t-1},  u_t = k s^t y_t(z).
 // Real parts k s^t j_t(z): power series for z < 1, downward (Miller)
-// recurrence normalised by j_0 = sin z / z otherwise.
+// recurrence otherwise, normalised by whichever of j_0 = sin z / z and
+// j_1 = sin z / z^2 - cos z / z is larger in magnitude (their zeros
+// interlace, so the normalisation never divides by a vanishing value:
+// at z = n pi, where j_0 vanishes, j_1 = -cos z / z).
 void scaled_hankel(double k, double s, double w, int tau, std::vector<double>& out) {
   out.assign(2 * (tau + 1), 0.0);
   const double z = k * w;
@@ -87,7 +90,8 @@ void scaled_hankel(double k, double s, double w, int tau, std::vector<double>& o
         for (int q = t - 1; q <= nstart + 1; ++q) j[q] *= 1e-250;
       }
     }
-    double scale = (sz / z) / j[0];
+    const double j0 = sz / z, j1 = sz / (z * z) - cz / z;
+    const double scale = std::fabs(j0) >= std::fabs(j1) ? j0 / j[0] : j1 / j[1];
     double st = 1.0;
     for (int t = 0; t <= tau; ++t) {
       out[2 * t] = k * st * j[t] * scale;

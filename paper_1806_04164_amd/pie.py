@@ -247,6 +247,12 @@ class Operator:
         check(lib().pie_operator_info(self.h, _lib.OI[what], ctypes.byref(v)))
         return v.value
 
+    def tau_level(self, l: int) -> int:
+        """Truncation number of Eq. (5) at level l (PIE_OI_TAU_LEVEL)."""
+        v = ctypes.c_int64()
+        check(lib().pie_operator_info(self.h, 100 + int(l), ctypes.byref(v)))
+        return v.value
+
     def level(self, l: int):
         s, k, d = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         check(lib().pie_operator_level(self.h, l, ctypes.byref(s), ctypes.byref(k), ctypes.byref(d)))

@@ -19,6 +19,8 @@ def _mesh(spec):
         return synth.uneven_batch()[arg].mesh()
     if kind == "patch":
         return synth.patch(arg)
+    if kind == "icosphere":
+        return synth.icosphere(arg)
     raise ValueError(kind)
 
 

@@ -126,8 +126,16 @@ def test_operator_argument_validation_without_gpu():
     L.pie_options_default(ctypes.byref(oo))
     oo.far_prec, oo.tau, oo.x = _lib.PIE_FP32, 7, 0.05
     assert L.pie_operator_create(m.h, tr.h, 1e6, ctypes.byref(oo), None, ctypes.byref(h)) == _lib.PIE_ERR_PRECISION
-    # outside the low-frequency regime
+    # level-3 boxes beyond what the truncation numbers cover: 6 wavelengths
+    # (k d_3 = 9.4) by default; 2 wavelengths (k d_3 = 3.1) with the FP32 far
+    # field (k d_3 <= 1) or a caller's tau = 7 (k d_3 <= 1.6)
     assert L.pie_operator_create(m.h, tr.h, 3e9, ctypes.byref(o), None, ctypes.byref(h)) == _lib.PIE_ERR_UNSUPPORTED
+    for far, tau in ((_lib.PIE_FP32, 0), (_lib.PIE_FP64, 7)):
+        oo = _lib.pie_options()
+        L.pie_options_default(ctypes.byref(oo))
+        oo.far_prec, oo.tau = far, tau
+        assert L.pie_operator_create(m.h, tr.h, 1e9, ctypes.byref(oo), None, ctypes.byref(h)) == \
+            _lib.PIE_ERR_UNSUPPORTED
     # tree built for another mesh
     m2 = pie.Mesh(V, T)
     assert L.pie_operator_create(m2.h, tr.h, 1e6, ctypes.byref(o), None, ctypes.byref(h)) == _lib.PIE_ERR_ARG

@@ -34,6 +34,58 @@ def test_kernel_all_offsets(kd):
     assert errs.max() < 1e-2
 
 
+@pytest.mark.parametrize("kd,tau", [(3.1, 9), (4.7, 10)])
+def test_kernel_all_offsets_large_boxes(kd, tau):
+    """Boxes of 0.5 and 0.75 wavelength (s = 1, Eq. (5) the ordinary
+    translation function): tau = 9 and 10 hold the kernel to 1e-3 rms at
+    every one-box-buffer offset, against the exact Green's function."""
+    p = mlfma.Params(tau=tau, x=0.08)
+    d = 1.0
+    k = kd / d
+    s = mlfma.scale_factor(k, d, p.x)
+    assert s == 1.0
+    rng = np.random.default_rng(6)
+    errs = []
+    for o in octree.far_offsets():
+        co = o * d
+        for _ in range(3):
+            r = co + (rng.random(3) - 0.5) * d
+            rp = (rng.random(3) - 0.5) * d
+            R = np.linalg.norm(r - rp)
+            g = np.exp(1j * k * R) / (4 * np.pi * R)
+            errs.append(abs(mlfma.kernel(k, s, p, r, rp, co, np.zeros(3)) - g) / abs(g))
+    errs = np.array(errs)
+    assert np.sqrt(np.mean(errs ** 2)) < 1e-3
+
+
+def test_per_level_truncation_two_wavelengths():
+    """A 2-wavelength sphere on 4 levels: the coarse level (k d_3 = 3.1)
+    takes tau = 9, the finest (k d_4 = 1.6) tau = 7, both with the k-space
+    samples of tau = 9.  Sampled rows of the dense matrix agree per
+    sub-operator within 1e-3 (uniform tau = 7 leaves 9.7e-4 there, uniform
+    tau = 9 2.6e-4); with the same tau at every level the per-level path is
+    the uniform one bit for bit."""
+    V, T = synth.icosphere(4)
+    prob = mom.Problem(V, T, 2.0 * synth.C0 / synth.DIAMETER)
+    N, E = prob.N, prob.mesh.nE
+    rng = np.random.default_rng(5)
+    rows = np.sort(np.concatenate([rng.choice(E, 24, replace=False), E + rng.choice(N - E, 24, replace=False)]))
+    x = synth.complex_gaussian(N, 1, 3)[:, 0]
+    Zr = prob.zblock(rows, np.arange(N))
+    M = mlfma.MLFMA(prob, 4, mlfma.Params(tau=9, x=0.08, level_tau=((4, 7),)))
+    assert abs(prob.k * M.d[3] - 3.14) < 0.05 and abs(prob.k * M.d[4] - 1.57) < 0.05
+    for name, sl in (("J", slice(0, E)), ("A", slice(E, None))):
+        xm = np.zeros_like(x)
+        xm[sl] = x[sl]
+        y = M.matvec_rows(xm, rows)
+        r = Zr @ xm
+        for rs in (rows < E, rows >= E):
+            assert np.linalg.norm(y[rs] - r[rs]) <= 1e-3 * np.linalg.norm(r[rs])
+    Mu = mlfma.MLFMA(prob, 4, mlfma.Params(tau=9, x=0.08))
+    Me = mlfma.MLFMA(prob, 4, mlfma.Params(tau=9, x=0.08, level_tau=((3, 9), (4, 9))))
+    assert np.array_equal(Mu.matvec_rows(x, rows[:6]), Me.matvec_rows(x, rows[:6]))
+
+
 @pytest.fixture(scope="module")
 def op():
     V, T = synth.icosphere(3, jitter=0.05, seed=2)

@@ -125,11 +125,13 @@ struct DevNear {
   int32_t ntask;
   const struct NearTaskDesc* tdesc;  // [ntask] one row panel per SpMM work unit
   const int32_t* pcol;      // task -> partial-sum slot of its column sums (a < b)
-  const int32_t* slot_ptr;  // [nbL+1] slot ranges of the boxes
-  const int32_t* ubase;     // [nbL] box-order unknown of each box's first slot
-  const int32_t* row_ptr;   // [nbL+1] blocks whose a is the box
-  const int32_t* col_ptr;   // [nbL+1] into col_blk
-  const int32_t* col_blk;   // tasks of blocks (a < b) whose b is the box
+  // near boxes: a finest box's slots in runs of at most 128 (its box order)
+  const int32_t* slot_ptr;  // [nv+1] slot ranges of the near boxes
+  const int32_t* ubase;     // [nv] box-order unknown of each near box's first slot
+  const int32_t* vptr;      // [nbL+1] near boxes of each finest box (slot run c = chunk c of 128)
+  const int32_t* row_ptr;   // [nv+1] blocks whose a is the near box
+  const int32_t* col_ptr;   // [nv+1] into col_blk
+  const int32_t* col_blk;   // tasks of blocks (a < b) whose b is the near box
 };
 
 // One tree level.

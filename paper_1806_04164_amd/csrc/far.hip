@@ -888,22 +888,48 @@ __global__ void __launch_bounds__(512) k_translate_set(TranslateSet ts, int Q, i
 // is written to its canonical position (conjugated for the adjoint); phi
 // goes to a per-triangle array for the divergence testing of the RWG rows.
 // ---------------------------------------------------------------------------
-// Near-field partial-sum slots of finest box b in a fixed order: the
-// RWG-RWG structure's row and column slots (nslotJ of them), then the
-// triangle-triangle structure's (nslot in all); staged in LDS.
+// Staged near-field join list of finest box b.  For each of its near boxes
+// (chunk c of 128 slots of a structure) the row and then the column
+// partial-sum slots are listed, each as (slot - 128 c), so that entry + ul
+// addresses the row of the box's unknown ul; kofs[0..nJ] are the list
+// ranges of the RWG chunks and kofs[nJ + 1 .. nJ + 1 + nT] those of the
+// triangle chunks (the list itself starts at kofs + nJ + nT + 2, returned in
+// slots).  Called by every thread of the workgroup (it holds a barrier).
 __device__ __forceinline__ void near_join_slots(const DevNear& NJ, const DevNear& NT, int b, bool do_near,
-                                                int32_t* slots, int& nslotJ, int& nslot) {
-  const int nrowJ = do_near ? NJ.row_ptr[b + 1] - NJ.row_ptr[b] : 0;
-  nslotJ = do_near ? nrowJ + NJ.col_ptr[b + 1] - NJ.col_ptr[b] : 0;
-  const int nrowT = do_near ? NT.row_ptr[b + 1] - NT.row_ptr[b] : 0;
-  nslot = nslotJ + (do_near ? nrowT + NT.col_ptr[b + 1] - NT.col_ptr[b] : 0);
-  for (int e = threadIdx.x; e < nslot; e += blockDim.x) {
-    if (e < nslotJ)
-      slots[e] = e < nrowJ ? NJ.prow[NJ.row_ptr[b] + e] : NJ.pcol[NJ.col_blk[NJ.col_ptr[b] + e - nrowJ]];
-    else {
-      const int f = e - nslotJ;
-      slots[e] = f < nrowT ? NT.prow[NT.row_ptr[b] + f] : NT.pcol[NT.col_blk[NT.col_ptr[b] + f - nrowT]];
+                                                int32_t* kofs, int32_t*& slots, int& nJ) {
+  const int vJ0 = NJ.vptr[b], vT0 = NT.vptr[b];
+  nJ = NJ.vptr[b + 1] - vJ0;
+  const int nT = NT.vptr[b + 1] - vT0;
+  slots = kofs + nJ + nT + 2;
+  if (threadIdx.x == 0) {
+    int k = 0;
+    for (int c = 0; c < nJ; ++c) {
+      kofs[c] = k;
+      const int v = vJ0 + c;
+      if (do_near) k += (NJ.row_ptr[v + 1] - NJ.row_ptr[v]) + (NJ.col_ptr[v + 1] - NJ.col_ptr[v]);
     }
+    kofs[nJ] = k;
+    for (int c = 0; c < nT; ++c) {
+      kofs[nJ + 1 + c] = k;
+      const int v = vT0 + c;
+      if (do_near) k += (NT.row_ptr[v + 1] - NT.row_ptr[v]) + (NT.col_ptr[v + 1] - NT.col_ptr[v]);
+    }
+    kofs[nJ + 1 + nT] = k;
+  }
+  __syncthreads();
+  const int total = kofs[nJ + 1 + nT], nJs = kofs[nJ];
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c = 0, sl;
+    if (e < nJs) {
+      while (e >= kofs[c + 1]) ++c;
+      const int v = vJ0 + c, f = e - kofs[c], nrow = NJ.row_ptr[v + 1] - NJ.row_ptr[v];
+      sl = f < nrow ? NJ.prow[NJ.row_ptr[v] + f] : NJ.pcol[NJ.col_blk[NJ.col_ptr[v] + f - nrow]];
+    } else {
+      while (e >= kofs[nJ + 2 + c]) ++c;
+      const int v = vT0 + c, f = e - kofs[nJ + 1 + c], nrow = NT.row_ptr[v + 1] - NT.row_ptr[v];
+      sl = f < nrow ? NT.prow[NT.row_ptr[v] + f] : NT.pcol[NT.col_blk[NT.col_ptr[v] + f - nrow]];
+    }
+    slots[e] = sl - 128 * c;
   }
 }
 
@@ -940,7 +966,7 @@ template <typename TN, typename RV>
 __device__ __forceinline__ void receive_unknown(const DevInc& I, const DevBasis& B, int u, int ul, int nJb, int r,
                                                 int c0, int W, bool do_far, bool do_near, bool conj_out,
                                                 const cx<TN>* __restrict__ partJ, const cx<TN>* __restrict__ partT,
-                                                const int32_t* slots, int nslotJ, int nslot, RV rv,
+                                                const int32_t* slots, const int32_t* kofs, int nJ, RV rv,
                                                 cx<double>* __restrict__ y, int ldy, cx<double>* __restrict__ phi) {
   const double mu0 = 4.0e-7 * 3.14159265358979323846;
   const int cu = B.perm[u];
@@ -963,7 +989,7 @@ __device__ __forceinline__ void receive_unknown(const DevInc& I, const DevBasis&
         val.im += mu0 * sv * t.im;
       }
     }
-    if (do_near) near_join(partJ, slots, 0, nslotJ, ul, W, col, val);
+    if (do_near) near_join(partJ, slots, kofs[ul >> 7], kofs[(ul >> 7) + 1], ul, W, col, val);
     if (conj_out) val.im = -val.im;
     y[(size_t)cu * ldy + col] = val;
   } else {
@@ -973,9 +999,9 @@ __device__ __forceinline__ void receive_unknown(const DevInc& I, const DevBasis&
       ps = rv(0, 5);
     }
     if (do_near) {
-      const int lt = ul - nJb;
-      near_join(partT, slots, nslotJ, nslot, lt, 2 * W, col, ph);
-      near_join(partT, slots, nslotJ, nslot, lt, 2 * W, (size_t)W + col, ps);
+      const int lt = ul - nJb, k0 = kofs[nJ + 1 + (lt >> 7)], k1 = kofs[nJ + 2 + (lt >> 7)];
+      near_join(partT, slots, k0, k1, lt, 2 * W, col, ph);
+      near_join(partT, slots, k0, k1, lt, 2 * W, (size_t)W + col, ps);
     }
     if (conj_out) {
       ph.im = -ph.im;
@@ -1003,13 +1029,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 
   cx<TF>* Gs = (cx<TF>*)smem;                              // [Q][5][RC]
   cx<TF>* red = Gs + (size_t)Q * ncol;                     // [ni][6][RC]: A, Bx, By, Bz, Cs, Du
   int32_t* pair = (int32_t*)(red + (size_t)ni * 6 * RC);  // [Qh] antipode of each stored sample
-  int32_t* slots = pair + Q;                               // near-field partial-sum slots
-  int nslotJ, nslot;
-  near_join_slots(NJ, NT, b, do_near, slots, nslotJ, nslot);
+  int32_t* kofs = pair + Q;                                // near-field join ranges and slots
+  int32_t* slots;
+  int nJ;
+  near_join_slots(NJ, NT, b, do_near, kofs, slots, nJ);
   if (do_far)
     for (int q = Qh + threadIdx.x; q < Q; q += blockDim.x) pair[anti[q]] = q;
   const int u0 = I.uptr[b], nu = I.uptr[b + 1] - u0;
-  const int nJb = NJ.slot_ptr[b + 1] - NJ.slot_ptr[b];  // RWG functions come first in a box
+  const int nJb = NJ.slot_ptr[NJ.vptr[b + 1]] - NJ.slot_ptr[NJ.vptr[b]];  // RWG functions come first in a box
   for (int c0 = 0; c0 < W; c0 += RC) {
     if (c0 > 0) __syncthreads();
     if (do_far) {
@@ -1098,8 +1125,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 
         const cx<TF> v = red[(size_t)(I.uj[2 * u + h] - j0) * 6 * RC + o * RC + r];
         return mk((double)v.re, (double)v.im);
       };
-      receive_unknown<TN>(I, B, u, ul, nJb, r, c0, W, do_far, do_near, conj_out, partJ, partT, slots, nslotJ,
-                          nslot, rv, y, ldy, phi);
+      receive_unknown<TN>(I, B, u, ul, nJb, r, c0, W, do_far, do_near, conj_out, partJ, partT, slots, kofs,
+                          nJ, rv, y, ldy, phi);
     }
   }
 }
@@ -1151,9 +1178,10 @@ __global__ void __launch_bounds__(256) k_mreceive(DevInc I, DevBasis B, DevNear 
   double* pa = (double*)smem;            // [2][64][48] partial sums of the K split
   cx<double>* red = (cx<double>*)smem;   // [ni][6][MR_COLS]
   int32_t* pairt = (int32_t*)(smem + buf);  // [Q] antipode of each stored sample
-  int32_t* slots = pairt + Q;                 // near-field partial-sum slots
-  int nslotJ, nslot;
-  near_join_slots(NJ, NT, b, do_near, slots, nslotJ, nslot);
+  int32_t* kofs = pairt + Q;                  // near-field join ranges and slots
+  int32_t* slots;
+  int nJ;
+  near_join_slots(NJ, NT, b, do_near, kofs, slots, nJ);
   const bool paired = Qh < Q;
   for (int q = Qh + threadIdx.x; q < Q; q += blockDim.x) pairt[anti[q]] = q;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kq = lane >> 4, jl = lane & 15;
@@ -1244,13 +1272,13 @@ __global__ void __launch_bounds__(256) k_mreceive(DevInc I, DevBasis B, DevNear 
   }
   __syncthreads();
   const int u0 = I.uptr[b], nu = I.uptr[b + 1] - u0;
-  const int nJb = NJ.slot_ptr[b + 1] - NJ.slot_ptr[b];
+  const int nJb = NJ.slot_ptr[NJ.vptr[b + 1]] - NJ.slot_ptr[NJ.vptr[b]];
   for (int e = threadIdx.x; e < nu * MR_COLS; e += blockDim.x) {
     const int ul = e / MR_COLS, r = e - ul * MR_COLS;
     if (c0 + r >= W) continue;
     const int u = u0 + ul;
     auto rv = [&](int h, int o) { return red[((size_t)(I.uj[2 * u + h] - j0) * 6 + o) * MR_COLS + r]; };
-    receive_unknown<TN>(I, B, u, ul, nJb, r, c0, W, do_far, do_near, conj_out, partJ, partT, slots, nslotJ, nslot,
+    receive_unknown<TN>(I, B, u, ul, nJb, r, c0, W, do_far, do_near, conj_out, partJ, partT, slots, kofs, nJ,
                         rv, y, ldy, phi);
   }
 }

@@ -41,6 +41,7 @@ struct pie_op {
   int pw = 1;  // RHS columns per MVM pass (workspace width): min(max_rhs, kPassMax)
   int maxinc = 0;   // most (box, triangle) incidences of a finest box
   int maxjoin = 0;  // longest near-field join list of a finest box
+  int lds_budget = 65536;  // dynamic LDS of the single-column aggregation and reception
   int nsplit = 1;  // aggregation incidence-loop split (fixed per operator: RHS-batch-independent order)
   // device geometry
   double *dV = nullptr, *dP = nullptr, *dW = nullptr, *dC = nullptr, *dN = nullptr;
@@ -266,15 +267,34 @@ pie_status upload_tables(pie_op* op, const std::vector<double>& khat, const std:
 }
 
 // One near-field structure (kind 0: RWG-RWG, 1: triangle-triangle) over
-// per-box slot counts cnt: the slots of box b are [sptr[b], sptr[b] + cnt[b])
-// in the structure's slot order and start at box-order unknown ubase[b].
-// Stored blocks (a <= b, both boxes with slots) are grouped by row box and
-// split into row panels of at most one LDS panel (2048 FP32 / 1024 FP64
-// entries), one SpMM work unit each; row_ptr / col_ptr receive the per-box
-// join ranges (host copies).
-pie_status build_near(pie_op* op, const Tree& t, int kind, const std::vector<int32_t>& cnt,
-                      const std::vector<int32_t>& ubase, DevNear& out, int64_t& stored, int64_t& entries,
-                      int64_t& nslots, std::vector<int32_t>& row_ptr, std::vector<int32_t>& col_ptr) {
+// per-box slot counts cnt.  A finest box's slots are cut into near boxes of
+// at most kNearBox slots (runs of its box order), so that every stored block
+// fits the SpMM's 128-row / 128-column tiles whatever a finest box holds;
+// near box v covers slots [sptr[v], sptr[v] + n_v) starting at box-order
+// unknown ubase_v, and vptr[b] .. vptr[b + 1] are the near boxes of finest
+// box b.  Stored blocks (v <= w, the finest boxes near) are grouped by row
+// near box and split into row panels of at most one LDS panel (2048 FP32 /
+// 1024 FP64 entries), one SpMM work unit each; row_ptr / col_ptr receive the
+// per-near-box join ranges and vptr the near boxes of each finest box (host
+// copies).
+constexpr int kNearBox = 128;
+// Most RWG functions or triangles in one finest box.
+constexpr int kMaxBoxSlots = 32 * kNearBox;
+pie_status build_near(pie_op* op, const Tree& t, int kind, const std::vector<int32_t>& cnt_box,
+                      const std::vector<int32_t>& ubase_box, DevNear& out, int64_t& stored, int64_t& entries,
+                      int64_t& nslots, std::vector<int32_t>& row_ptr, std::vector<int32_t>& col_ptr,
+                      std::vector<int32_t>& vptr) {
+  const int nbox = (int)cnt_box.size();
+  std::vector<int32_t> cnt, ubase, vreal;
+  vptr.assign(nbox + 1, 0);
+  for (int b = 0; b < nbox; ++b) {
+    for (int c = 0; c * kNearBox < cnt_box[b]; ++c) {
+      cnt.push_back(std::min(kNearBox, cnt_box[b] - c * kNearBox));
+      ubase.push_back(ubase_box[b] + c * kNearBox);
+      vreal.push_back(b);
+    }
+    vptr[b + 1] = (int32_t)cnt.size();
+  }
   const int nbL = (int)cnt.size();
   std::vector<int32_t> sptr(nbL + 1, 0);
   for (int b = 0; b < nbL; ++b) sptr[b + 1] = sptr[b] + cnt[b];
@@ -287,8 +307,9 @@ pie_status build_near(pie_op* op, const Tree& t, int kind, const std::vector<int
   std::vector<std::vector<int32_t>> cols(nbL);
   int64_t off = 0, slot = 0, ent = 0;
   for (int a = 0; a < nbL; ++a) {
-    for (int64_t k = t.near_ptr[a]; k < t.near_ptr[a + 1]; ++k) {
-      const int b = (int)t.near_idx[k];
+    const int A = vreal[a];
+    for (int64_t k = t.near_ptr[A]; k < t.near_ptr[A + 1]; ++k)
+    for (int b = vptr[t.near_idx[k]]; b < vptr[t.near_idx[k] + 1]; ++b) {
       const int na = cnt[a], nb = cnt[b];
       if (b < a || na == 0 || nb == 0) continue;
       const int id = (int)ba.size();
@@ -346,13 +367,14 @@ pie_status build_near(pie_op* op, const Tree& t, int kind, const std::vector<int
   int64_t* dbo;
   NearTaskDesc* dtd;
   pie_status s;
+  int32_t* dvp;
   if ((s = upload(op, &dba, ba)) || (s = upload(op, &dbb, bb)) || (s = upload(op, &dbo, boff)) ||
       (s = upload(op, &dprow, prow)) || (s = upload(op, &dsp, sptr)) || (s = upload(op, &dub, ubase)) ||
       (s = upload(op, &drp, row_ptr)) || (s = upload(op, &dcp, col_ptr)) || (s = upload(op, &dcb, col_blk)) ||
-      (s = upload(op, &dtd, tdesc)) || (s = upload(op, &dtpc, tpc)))
+      (s = upload(op, &dtd, tdesc)) || (s = upload(op, &dtpc, tpc)) || (s = upload(op, &dvp, vptr)))
     return s;
   out = DevNear{kind, (int32_t)ba.size(), dba, dbb, dbo, dprow, (int32_t)tdesc.size(), dtd, dtpc,
-                dsp, dub, drp, dcp, dcb};
+                dsp, dub, dvp, drp, dcp, dcb};
   return PIE_OK;
 }
 
@@ -438,14 +460,15 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
       }
     }
   for (int b = 0; b < nbL; ++b)
-    if (cntJ[b] > 128 || cntT[b] > 128) {
-      set_error("a finest box holds more than 128 RWG functions or 128 triangles; use more levels");
+    if (cntJ[b] > kMaxBoxSlots || cntT[b] > kMaxBoxSlots) {
+      set_error("a finest box holds more than " + std::to_string(kMaxBoxSlots) +
+                " RWG functions or triangles; use more levels");
       return PIE_ERR_UNSUPPORTED;
     }
   if ((s = upload(op, &op->dPermJ, permJ)) || (s = upload(op, &op->dPermT, permT)) ||
       (s = upload(op, &op->dBoxPtr, box_ptr)))
     return s;
-  std::vector<int32_t> row_ptr_J, col_ptr_J, row_ptr_T, col_ptr_T;
+  std::vector<int32_t> row_ptr_J, col_ptr_J, row_ptr_T, col_ptr_T, vptr_J, vptr_T;
   int64_t entJ = 0, entT = 0;
   {
     std::vector<int32_t> ubJ(nbL), ubT(nbL);
@@ -453,8 +476,10 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
       ubJ[b] = box_ptr[b];
       ubT[b] = box_ptr[b] + cntJ[b];
     }
-    if ((s = build_near(op, t, 0, cntJ, ubJ, op->NJ, op->near_stored_J, entJ, op->nslots_J, row_ptr_J, col_ptr_J)) ||
-        (s = build_near(op, t, 1, cntT, ubT, op->NT, op->near_stored_T, entT, op->nslots_T, row_ptr_T, col_ptr_T)))
+    if ((s = build_near(op, t, 0, cntJ, ubJ, op->NJ, op->near_stored_J, entJ, op->nslots_J, row_ptr_J, col_ptr_J,
+                        vptr_J)) ||
+        (s = build_near(op, t, 1, cntT, ubT, op->NT, op->near_stored_T, entT, op->nslots_T, row_ptr_T, col_ptr_T,
+                        vptr_T)))
       return s;
   }
   op->near_entries = entJ + entT;
@@ -568,11 +593,17 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
       return s;
     op->I = DevInc{dip, dpw, dxc, drs, dpv, duj, dus, dupv, op->dBoxPtr, op->TD};
   }
-  // longest near-field join list of a finest box (partial-sum slots staged in LDS by the reception)
+  // longest near-field join list of a finest box (partial-sum slots of its
+  // near boxes and their ranges, staged in LDS by the reception)
   op->maxjoin = 0;
-  for (int b = 0; b < nbL; ++b)
-    op->maxjoin = std::max(op->maxjoin, (row_ptr_J[b + 1] - row_ptr_J[b]) + (col_ptr_J[b + 1] - col_ptr_J[b]) +
-                                            (row_ptr_T[b + 1] - row_ptr_T[b]) + (col_ptr_T[b + 1] - col_ptr_T[b]));
+  for (int b = 0; b < nbL; ++b) {
+    int n = (vptr_J[b + 1] - vptr_J[b]) + (vptr_T[b + 1] - vptr_T[b]) + 2;
+    for (int v = vptr_J[b]; v < vptr_J[b + 1]; ++v)
+      n += (row_ptr_J[v + 1] - row_ptr_J[v]) + (col_ptr_J[v + 1] - col_ptr_J[v]);
+    for (int v = vptr_T[b]; v < vptr_T[b + 1]; ++v)
+      n += (row_ptr_T[v + 1] - row_ptr_T[v]) + (col_ptr_T[v + 1] - col_ptr_T[v]);
+    op->maxjoin = std::max(op->maxjoin, n);
+  }
   // ---------------- levels
   op->lv.assign(L + 1, DevLevel{});
   op->s_l.assign(L + 1, 0.0);
@@ -777,8 +808,15 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
   s = op->far_prec == PIE_FP32 ? upload_tables<float>(op, khat, Tt, Ft, Pht)
                                : upload_tables<double>(op, khat, Tt, Ft, Pht);
   if (s) return s;
-  // ---------------- chunk width for the RHS loop (LDS budget 64 KiB)
+  // ---------------- chunk width for the RHS loop: LDS budget 64 KiB (four
+  // workgroups per CU); boxes with more incidences (coarse trees) take one
+  // column at a time with up to the device's per-workgroup LDS
   const int tfb = op->far_prec == PIE_FP32 ? 4 : 8;
+  int lds_max = 65536;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->device) != hipSuccess ||
+      lds_max < 65536)
+    lds_max = 65536;
+  op->lds_budget = 65536;
   op->rc = 0;
   for (int rc : {4, 2, 1}) {
     if (rc > op->max_rhs && rc > 1) continue;
@@ -788,6 +826,11 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
       op->rc = rc;
       break;
     }
+  }
+  if (op->rc == 0 && aggregate_smem(op->maxinc, Q, 1, 1, tfb) <= (size_t)lds_max &&
+      receive_smem(op->maxinc, Q, op->maxjoin, 1, tfb) <= (size_t)lds_max) {
+    op->rc = 1;
+    op->lds_budget = lds_max;
   }
   if (op->rc == 0) {
     set_error("a finest box has too many incidences for the LDS budget; use more levels");
@@ -850,7 +893,8 @@ pie_status build_operator(pie_op* op, hipStream_t st) {
     // aggregation: one lane per stored sample, nsplit incidence groups
     const int rcm = op->rc <= 1 ? 1 : (op->rc <= 2 ? 2 : 4);
     op->nsplit = 256 / op->Qh < 1 ? 1 : 256 / op->Qh;
-    while (op->nsplit > 1 && aggregate_smem(op->maxinc, Q, op->nsplit, rcm, tfb) > 65536) --op->nsplit;
+    while (op->nsplit > 1 && aggregate_smem(op->maxinc, Q, op->nsplit, rcm, tfb) > (size_t)op->lds_budget)
+      --op->nsplit;
     unsigned char* mt;
     double* dkh;
     if ((s = dalloc(op, &mt, (size_t)op->ninc * op->Qh * 4 * cxf)) || (s = upload(op, &dkh, khat)) ||

@@ -45,12 +45,12 @@ def sampled_rows(jobs, processes=None):
     """jobs: list of (mesh spec, freq, rows, xseed, R); returns, per job, a
     dict {"J": Z[rows] x_J, "A": Z[rows] x_A} with x the seeded complex
     Gaussian input split into its RWG (J) and pulse (A) parts."""
-    n = processes or min(8, os.cpu_count() or 1, len(jobs))
     # one job per row so that large meshes spread over the workers
     flat = []
     for j, (spec, freq, rows, xseed, R) in enumerate(jobs):
         for r in rows:
             flat.append((j, (spec, freq, [int(r)], xseed, R)))
+    n = processes or min(16, os.cpu_count() or 1, len(flat))
     ctx = mp.get_context("spawn")
     with ctx.Pool(n) as pool:
         res = pool.map(_rows_job, [a for _, a in flat], chunksize=1)

@@ -72,7 +72,7 @@ def test_headline_workload_sampled_rows():
     op64 = pie.Operator(m, tr, w.freq, near_prec=PIE_FP64, far_prec=PIE_FP64)
     N = opm.N
     E = m.sizes()[0]
-    rows = _rows(N, E, 24, 24, 7)
+    rows = _rows(N, E, 64, 64, 7)
     ref = sampled_rows([(("workload", w.name), w.freq, rows, 21, 1)])[0]
     x = synth.complex_gaussian(N, 1, 21)
     for name, op in (("mixed", opm), ("fp64", op64)):
@@ -88,7 +88,7 @@ def test_batched_workload_sampled_rows():
     m, tr, op = _workload_op(w, PIE_FP32, PIE_FP64, 64)
     N = op.N
     E = m.sizes()[0]
-    rows = _rows(N, E, 8, 8, 8)
+    rows = _rows(N, E, 32, 32, 8)
     ref = sampled_rows([(("workload", w.name), w.freq, rows, 22, 64)])[0]
     x = synth.complex_gaussian(N, 64, 22)
     op.autotune(torch.from_numpy(x).cuda(), reps=2)

@@ -622,6 +622,54 @@ __device__ __forceinline__ void mshift_gemm(const double* Fs, int Q, const bool 
   }
 }
 
+// The same product with A read from the global filter table (rows q0 ..
+// q0 + 31 of the output, clamped to the table; rows past Q are never
+// stored, and K steps past Q meet a zero B), so that the workgroup keeps no
+// filter block in LDS; A is double-buffered with B.
+template <int KU, typename T, typename FE, typename VA, typename PRE>
+__device__ __forceinline__ void mshift_gemm_ga(const double* __restrict__ tab, int q0, int Q,
+                                               const bool (&col_ok)[2], FE fetch, VA value, PRE pre,
+                                               f64x4 (&acc)[2][2]) {
+  const int lane = threadIdx.x & 63, kq = lane >> 4, jl = lane & 15;
+  const int kp = (Q + 3) & ~3, kb = 4 * KU, nbat = (kp + kb - 1) / kb;
+  const int ra = min(q0 + jl, Q - 1), rb = min(q0 + 16 + jl, Q - 1);
+  T b0[KU][2], b1[KU][2];
+  double a0s[KU][2], a1s[KU][2];
+  auto get = [&](T (&bv)[KU][2], double (&av)[KU][2], int k0) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int k = min(k0 + 4 * u + kq, Q - 1);
+      av[u][0] = tab[(size_t)k * Q + ra];
+      av[u][1] = tab[(size_t)k * Q + rb];
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) bv[u][ct] = fetch(ct, k);
+    }
+  };
+  auto mul = [&](const T (&bv)[KU][2], const double (&av)[KU][2], int k0) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      if (k0 + 4 * u >= kp) break;
+      const int k = k0 + 4 * u + kq;
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+        if (col_ok[ct]) {
+          const double bb = k < Q ? value(ct, k, bv[u][ct]) : 0.0;
+          acc[0][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][0], bb, acc[0][ct], 0, 0, 0);
+          acc[1][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][1], bb, acc[1][ct], 0, 0, 0);
+        }
+    }
+  };
+  get(b0, a0s, 0);
+  pre();
+  for (int n = 0; n < nbat; n += 2) {
+    if (n + 1 < nbat) get(b1, a1s, (n + 1) * kb);
+    mul(b0, a0s, n * kb);
+    if (n + 1 >= nbat) break;
+    if (n + 2 < nbat) get(b0, a0s, (n + 2) * kb);
+    mul(b1, a1s, (n + 1) * kb);
+  }
+}
+
 // acc -> Ds[row][col]
 __device__ __forceinline__ void mshift_store(const f64x4 (&acc)[2][2], double* Ds) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -634,13 +682,12 @@ __device__ __forceinline__ void mshift_store(const f64x4 (&acc)[2][2], double* D
         Ds[(t * 16 + (lane >> 4) + 4 * v) * MS_COLS + w * 32 + ct * 16 + (lane & 15)] = acc[t][ct][v];
 }
 
-__global__ void __launch_bounds__(256) k_mshift_up(DevLevel Lp, DevLevel Lc, const cx<double>* __restrict__ Sc,
+__global__ void __launch_bounds__(256, 3) k_mshift_up(DevLevel Lp, DevLevel Lc, const cx<double>* __restrict__ Sc,
                                                    cx<double>* __restrict__ Sp, const double* __restrict__ Ft,
                                                    const cx<double>* __restrict__ ph, int Q, int R, int ntile,
                                                    int nchunk) {
   extern __shared__ __align__(16) unsigned char smem[];
-  double* Fs = (double*)smem;                                            // filter block
-  double* Ds = Fs + mshift_smem(Q) / sizeof(double);                     // [MS_ROWS][MS_COLS] result
+  double* Ds = (double*)smem;                                            // [MS_ROWS][MS_COLS] result
   cx<double>* phs = (cx<double>*)(Ds + MS_ROWS * MS_COLS);               // [child][row] output phases
   int32_t* cps = (int32_t*)(phs + SHIFT_GROUP * MS_ROWS);                // child ranges of the parents
   ShiftItem it;
@@ -669,12 +716,11 @@ __global__ void __launch_bounds__(256) k_mshift_up(DevLevel Lp, DevLevel Lc, con
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
-    mshift_gemm<8, double>(
-        Fs, Q, col_ok, [&](int ct, int k) { return S[base[ct] + (size_t)k * 10]; },
+    mshift_gemm_ga<4, double>(
+        Ft, q0, Q, col_ok, [&](int ct, int k) { return S[base[ct] + (size_t)k * 10]; },
         [&](int ct, int, double v) { return valid[ct] ? v : 0.0; },
         [&] {
-          if (r == r0) {  // the filter block, phases and child ranges, once for all columns
-            mshift_stage(Ft, Fs, Q, q0);
+          if (r == r0) {  // phases and child ranges, once for all columns
             for (int e = threadIdx.x; e < nch * nq; e += blockDim.x) {
               const int ci = e / nq, i = e - ci * nq;
               phs[ci * MS_ROWS + i] = ph[(size_t)Lc.octant[c0 + ci] * Q + q0 + i];
@@ -700,14 +746,13 @@ __global__ void __launch_bounds__(256) k_mshift_up(DevLevel Lp, DevLevel Lc, con
   }
 }
 
-__global__ void __launch_bounds__(256) k_mshift_down(DevLevel Lc, const cx<double>* __restrict__ Gp,
+__global__ void __launch_bounds__(256, 3) k_mshift_down(DevLevel Lc, const cx<double>* __restrict__ Gp,
                                                      cx<double>* __restrict__ Gc, const double* __restrict__ F,
                                                      const cx<double>* __restrict__ ph, int Q, int R, int ntile,
                                                      int nchunk) {
   extern __shared__ __align__(16) unsigned char smem[];
-  double* Fs = (double*)smem;                                 // filter block
-  double* Ds = Fs + mshift_smem(Q) / sizeof(double);          // [MS_ROWS][MS_COLS] result
-  cx<double>* phs = (cx<double>*)(Ds + MS_ROWS * MS_COLS);    // [8][Q] phases
+  double* Fs = (double*)smem;                                       // filter block
+  cx<double>* phs = (cx<double>*)(Fs + mshift_smem(Q) / sizeof(double));  // [8][Q] phases
   const int ng = (Lc.nb + SHIFT_GROUP - 1) / SHIFT_GROUP;
   ShiftItem it;
   if (!shift_item(ng, ntile, nchunk, MS_ROWS, it)) return;
@@ -715,7 +760,7 @@ __global__ void __launch_bounds__(256) k_mshift_down(DevLevel Lc, const cx<doubl
   const int nq = min(MS_ROWS, Q - q0);
   const int c0 = it.g * SHIFT_GROUP, c1 = min(Lc.nb, c0 + SHIFT_GROUP);
   const int ncols = 10 * (c1 - c0);
-  const int w = threadIdx.x >> 6, jl = threadIdx.x & 15;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, jl = threadIdx.x & 15;
   const int r0 = it.r * MS_RCH, r1 = min(R, r0 + MS_RCH);
   for (int r = r0; r < r1; ++r) {
     const cx<double>* gp[2];
@@ -747,20 +792,31 @@ __global__ void __launch_bounds__(256) k_mshift_down(DevLevel Lc, const cx<doubl
           if (r == r0) {  // the filter block and phases, once for all columns
             mshift_stage(F, Fs, Q, q0);
             for (int e = threadIdx.x; e < 8 * Q; e += blockDim.x) phs[e] = ph[e];
+            __syncthreads();
           }
-          __syncthreads();  // also: the previous column's result is consumed
         },
         acc);
-    mshift_store(acc, Ds);
-    __syncthreads();
-    const int m = (c1 - c0) * nq * 5;
-    for (int e = threadIdx.x; e < m; e += blockDim.x) {
-      const int ci = e / (nq * 5), rem = e - ci * nq * 5;
-      const int i = rem / 5, kk = rem - i * 5;
-      const double* d = Ds + i * MS_COLS + ci * 10 + 2 * kk;
-      cx<double>* o = Gc + (((size_t)(c0 + ci) * R + r) * Q + q0 + i) * 5 + kk;
-      *o = *o + mk(d[0], d[1]);
-    }
+    // epilogue from the accumulators: result register v of lane l is
+    // D[l / 16 + 4 v][l % 16] of tile (t, ct); columns 2m and 2m + 1 (adjacent
+    // lanes) are the real and imaginary parts of one complex value, which the
+    // even lane adds to the child's incoming pattern
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        if (!col_ok[ct]) continue;
+        const int col = w * 32 + ct * 16 + jl, ci = col / 10, rem = col - ci * 10;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double mine = acc[t][ct][v];
+          const double other = __shfl_xor(mine, 1);
+          const int i = t * 16 + (lane >> 4) + 4 * v;
+          if (!(lane & 1) && valid[ct] && i < nq) {
+            cx<double>* o = Gc + (((size_t)(c0 + ci) * R + r) * Q + q0 + i) * 5 + (rem >> 1);
+            *o = *o + mk(mine, other);
+          }
+        }
+      }
   }
 }
 
@@ -1384,8 +1440,8 @@ hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* S
       (force_mfma || Lp.nug * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS)) {
     const int ntile = (Q + MS_ROWS - 1) / MS_ROWS, nchunk = (R + MS_RCH - 1) / MS_RCH;
     const unsigned grid = 8u * (unsigned)(((Lp.nug + 7) / 8) * ntile * nchunk);
-    const size_t sm = mshift_smem(Q) + MS_ROWS * MS_COLS * sizeof(double) +
-                      SHIFT_GROUP * MS_ROWS * sizeof(cx<double>) + (SHIFT_GROUP + 1) * sizeof(int32_t);
+    const size_t sm = MS_ROWS * MS_COLS * sizeof(double) + SHIFT_GROUP * MS_ROWS * sizeof(cx<double>) +
+                      (SHIFT_GROUP + 1) * sizeof(int32_t);
     hipLaunchKernelGGL(k_mshift_up, dim3(grid), dim3(256), sm, st, Lp, Lc, (const cx<double>*)Sc,
                        (cx<double>*)Sp, (const double*)Ft, (const cx<double>*)ph, Q, R, ntile, nchunk);
     return hipGetLastError();
@@ -1404,7 +1460,7 @@ hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const
   if (sizeof(TF) == 8 && (force_mfma || ng * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS)) {
     const int ntile = (Q + MS_ROWS - 1) / MS_ROWS, nchunk = (R + MS_RCH - 1) / MS_RCH;
     const unsigned grid = 8u * (unsigned)(((ng + 7) / 8) * ntile * nchunk);
-    const size_t sm = mshift_smem(Q) + MS_ROWS * MS_COLS * sizeof(double) + 8 * (size_t)Q * sizeof(cx<double>);
+    const size_t sm = mshift_smem(Q) + 8 * (size_t)Q * sizeof(cx<double>);
     hipLaunchKernelGGL(k_mshift_down, dim3(grid), dim3(256), sm, st, Lc, (const cx<double>*)Gp, (cx<double>*)Gc,
                        (const double*)F, (const cx<double>*)ph, Q, R, ntile, nchunk);
     return hipGetLastError();

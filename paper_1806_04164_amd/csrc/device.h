@@ -167,7 +167,7 @@ constexpr int TRANSLATE_OFFSETS = 316;
 // Batched translation: boxes per group, samples per workgroup (one per
 // wavefront), columns per wavefront pass.
 constexpr int TG_BOXES = 4;
-constexpr int TG_Q = 8;
+constexpr int TG_Q = 4;
 constexpr int TG_COLS = 64;
 
 // (finest box, triangle) incidences: up to three RWG functions of the box

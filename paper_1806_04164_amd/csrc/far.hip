@@ -2,13 +2,15 @@
 // diagonal translation with the scaled plane waves of Eq. (4) and the
 // modified translation function of Eq. (5), disaggregation and reception.
 //
-// Pattern layout (outgoing S and incoming G of every level), box-major and
-// column-major within a box:
-//   P[((box * W + r) * Q + q) * 5 + c],  c in {Jx, Jy, Jz, sigma, u},
-// u = div J + w^2 eps0 sigma, W = the RHS columns of the pass.  For one
-// column a box's Q x 5 values are contiguous, so the translation's gather of
-// one source box by the Q sample lanes of a workgroup is a single
-// contiguous run for any W.
+// Pattern layouts of every level (W = the RHS columns of the pass, c in
+// {Jx, Jy, Jz, sigma, u}, u = div J + w^2 eps0 sigma), both box-major:
+//   outgoing S: S[((box * Q + q) * W + r) * 5 + c]   (sample-major)
+//   incoming G: G[((box * W + r) * Q + q) * 5 + c]   (column-major)
+// The translation reads every outgoing row about as many times as the
+// interaction list is long; sample-major, the W x 5 values of one (box,
+// sample) that a wavefront gathers are one contiguous run.  Its output, the
+// downward shifts and the reception take whole columns (Q x 5 contiguous).
+// With W = 1 the two layouts coincide.
 #include <algorithm>
 
 #include "device.h"
@@ -218,11 +220,11 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
 #pragma unroll
       for (int r = 0; r < RC; ++r)
         if (c0 + r < W) {
-          cx<TF>* o = S + (((size_t)b * W + c0 + r) * Q + sq) * 5;
+          cx<TF>* o = S + (((size_t)b * Q + sq) * W + c0 + r) * 5;
 #pragma unroll
           for (int k = 0; k < 5; ++k) o[k] = acc[k * RC + r];
           if (paired) {
-            cx<TF>* o2 = S + (((size_t)b * W + c0 + r) * Q + q2) * 5;
+            cx<TF>* o2 = S + (((size_t)b * Q + q2) * W + c0 + r) * 5;
 #pragma unroll
             for (int k = 0; k < 5; ++k) o2[k] = acc2[k * RC + r];
           }
@@ -354,12 +356,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       for (int v = 0; v < 4; ++v) {
         const int sv = rt * 16 + kq + 4 * v;
         if (sv < Qh) {
-          cx<double>* o = S + (((size_t)b * W + r) * Q + sv) * 5;
+          cx<double>* o = S + (((size_t)b * Q + sv) * W + r) * 5;
 #pragma unroll
           for (int k = 0; k < 5; ++k)
             o[k] = mk(acc[k][0][v] - acc[k][1][v], acc[k][2][v] + acc[k][3][v]);
           if (paired) {
-            cx<double>* o2 = S + (((size_t)b * W + r) * Q + pair[sv]) * 5;
+            cx<double>* o2 = S + (((size_t)b * Q + pair[sv]) * W + r) * 5;
 #pragma unroll
             for (int k = 0; k < 5; ++k)
               o2[k] = mk(acc[k][0][v] + acc[k][1][v], acc[k][2][v] - acc[k][3][v]);
@@ -464,8 +466,8 @@ __global__ void __launch_bounds__(256) k_shift_up(DevLevel Lp, DevLevel Lc,
 #pragma unroll
   for (int i = 0; i < SQT; ++i) acc[i] = mk<TF>(0, 0);
   if (act) {
-    const cx<TF>* s = Sc + (((size_t)c * R + r) * Q) * 5 + k;
-    shift_mac(Fs, qa, qb, [&](int qq) { return s[(size_t)qq * 5]; }, acc);
+    const cx<TF>* s = Sc + ((size_t)c * Q * R + r) * 5 + k;
+    shift_mac(Fs, qa, qb, [&](int qq) { return s[(size_t)qq * R * 5]; }, acc);
   }
   if (sl > 0) {
 #pragma unroll
@@ -489,7 +491,7 @@ __global__ void __launch_bounds__(256) k_shift_up(DevLevel Lp, DevLevel Lc,
     const int p = p0 + pl;
     cx<TF> v = mk<TF>(0, 0);
     for (int ch = Lp.child_ptr[p]; ch < Lp.child_ptr[p + 1]; ++ch) v = v + part[((ch - c0) * 5 + kk) * SQT + i];
-    Sp[(((size_t)p * R + r) * Q + q0 + i) * 5 + kk] = v;
+    Sp[(((size_t)p * Q + q0 + i) * R + r) * 5 + kk] = v;
   }
 }
 
@@ -541,21 +543,25 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
 
 // ---------------------------------------------------------------------------
 // FP64 shifts on the matrix cores.  The filter product is a real GEMM
-//   D[q][col] = sum_q' F[q][q'] B[q'][col],  col = (child, component, re/im),
-// over the ten real columns of each child of a group (at most SHIFT_GROUP
-// children, MS_COLS columns), in v_mfma_f64_16x16x4 tiles.  A workgroup owns
-// MS_ROWS = 32 output samples of one group and one RHS column; wave w holds
-// the 2 x 2 tiles of rows 0..31 and columns 32w .. 32w+31 (tiles past the
-// group's columns are skipped).  The filter block is staged in LDS (zeros
-// pad Q to whole tiles and K steps), B is read from the pattern array eight
-// K steps at a time, and the result goes through LDS to the epilogue:
-// upward, each child row is phased and the children of a parent are added
-// in Morton order; downward, the parent's pattern is phased as it is loaded
-// and the result is added to the child's incoming pattern.
+//   D[q][col] = sum_q' F[q][q'] B[q'][col]
+// in v_mfma_f64_16x16x4 tiles.  A workgroup owns MS_ROWS = 32 output samples
+// and MS_COLS = 128 real columns; wave w holds the 2 x 2 tiles of rows
+// 0..31 and columns 32w .. 32w+31 (tiles past the last column are skipped).
+// The filter block is staged in LDS (zeros pad Q to whole tiles and K
+// steps) and B is read from the pattern array eight K steps at a time.
+// Upward in batched passes (sample-major outgoing patterns), the columns
+// are a block of one child's sample row and the children are phased and
+// summed in registers (narrow passes: (child, component, re/im) of a group
+// of children, as downward); downward (column-major incoming patterns), the columns are (child,
+// component, re/im) of up to SHIFT_GROUP children for one RHS column, the
+// parent's pattern is phased as it is loaded and the result is added to the
+// child's incoming pattern.
 // Operand layout of v_mfma_f64_16x16x4 (64 lanes): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result register v of lane l is
 // D[l / 16 + 4 v][l % 16].
 // ---------------------------------------------------------------------------
+// Batched passes: W >= TB_MIN_COLS columns take the batched kernels.
+constexpr int TB_MIN_COLS = 16;
 constexpr int MS_ROWS = 32;
 constexpr int MS_COLS = 128;
 constexpr int MS_MIN_ITEMS = 256;  // (group, row block) items for the matrix-core path
@@ -682,7 +688,13 @@ __device__ __forceinline__ void mshift_store(const f64x4 (&acc)[2][2], double* D
         Ds[(t * 16 + (lane >> 4) + 4 * v) * MS_COLS + w * 32 + ct * 16 + (lane & 15)] = acc[t][ct][v];
 }
 
-__global__ void __launch_bounds__(256, 3) k_mshift_up(DevLevel Lp, DevLevel Lc, const cx<double>* __restrict__ Sc,
+// Upward shift on the matrix cores for narrow passes (W < TB_MIN_COLS): the
+// GEMM columns are (child, component, re/im) of the children of a group of
+// parents (at most SHIFT_GROUP children) for one RHS column; the result goes
+// through LDS, where each child row is phased and the children of a parent
+// are added in Morton order.  The filter rows are read from the global table
+// (no filter block in LDS).
+__global__ void __launch_bounds__(256, 3) k_mshift_up_groups(DevLevel Lp, DevLevel Lc, const cx<double>* __restrict__ Sc,
                                                    cx<double>* __restrict__ Sp, const double* __restrict__ Ft,
                                                    const cx<double>* __restrict__ ph, int Q, int R, int ntile,
                                                    int nchunk) {
@@ -709,7 +721,7 @@ __global__ void __launch_bounds__(256, 3) k_mshift_up(DevLevel Lp, DevLevel Lc, 
       col_ok[ct] = cbase < ncols;
       valid[ct] = col < ncols;
       const int ci = col / 10, rem = col - ci * 10;
-      base[ct] = valid[ct] ? (((size_t)(c0 + ci) * R + r) * Q) * 10 + rem : 0;
+      base[ct] = valid[ct] ? ((size_t)(c0 + ci) * Q * R + r) * 10 + rem : 0;
     }
     f64x4 acc[2][2];
 #pragma unroll
@@ -717,7 +729,7 @@ __global__ void __launch_bounds__(256, 3) k_mshift_up(DevLevel Lp, DevLevel Lc, 
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
     mshift_gemm_ga<4, double>(
-        Ft, q0, Q, col_ok, [&](int ct, int k) { return S[base[ct] + (size_t)k * 10]; },
+        Ft, q0, Q, col_ok, [&](int ct, int k) { return S[base[ct] + (size_t)k * R * 10]; },
         [&](int ct, int, double v) { return valid[ct] ? v : 0.0; },
         [&] {
           if (r == r0) {  // phases and child ranges, once for all columns
@@ -741,9 +753,87 @@ __global__ void __launch_bounds__(256, 3) k_mshift_up(DevLevel Lp, DevLevel Lc, 
         const double* d = Ds + i * MS_COLS + ci * 10 + 2 * kk;
         v = v + phs[ci * MS_ROWS + i] * mk(d[0], d[1]);
       }
-      Sp[(((size_t)(p0 + pl) * R + r) * Q + q0 + i) * 5 + kk] = v;
+      Sp[(((size_t)(p0 + pl) * Q + q0 + i) * R + r) * 5 + kk] = v;
     }
   }
+}
+
+// Upward shift on the matrix cores for batched passes (W >= TB_MIN_COLS,
+// sample-major outgoing patterns).  A workgroup owns one parent p, its
+// output rows q0 .. q0 + 31 and a block of MS_COLS real columns n of a
+// sample row (n = (RHS column, component, re/im), W x 10 values):
+//   S_p[q][n] = sum_{children c, Morton order} ph_c(q) sum_k F[q][k] S_c[k][n]
+// One child at a time: the filter product on the matrix cores (its B rows are
+// the child's sample rows, 16 lanes reading 16 consecutive values), then the
+// complex phase of the output row applied in registers (real and imaginary
+// parts of a value sit in adjacent lanes) as the child is added.
+__global__ void __launch_bounds__(256, 3) k_mshift_up(DevLevel Lp, DevLevel Lc, const cx<double>* __restrict__ Sc,
+                                                   cx<double>* __restrict__ Sp, const double* __restrict__ Ft,
+                                                   const cx<double>* __restrict__ ph, int Q, int R, int ntile,
+                                                   int nnb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* Fs = (double*)smem;                                              // filter block
+  cx<double>* phs = (cx<double>*)(Fs + mshift_smem(Q) / sizeof(double));   // [8][MS_ROWS] output phases
+  ShiftItem it;
+  if (!shift_item(Lp.nb, ntile, nnb, MS_ROWS, it)) return;
+  const int p = it.g, q0 = it.q0, nq = min(MS_ROWS, Q - q0);
+  const int c0 = Lp.child_ptr[p], nch = Lp.child_ptr[p + 1] - c0;
+  const int ncol = 10 * R, n0 = it.r * MS_COLS;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, jl = lane & 15;
+  int col[2];
+  bool col_ok[2], valid[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    const int cbase = n0 + w * 32 + ct * 16;
+    col_ok[ct] = cbase < ncol;
+    valid[ct] = cbase + jl < ncol;
+    col[ct] = valid[ct] ? cbase + jl : 0;
+  }
+  mshift_stage(Ft, Fs, Q, q0);
+  for (int e = threadIdx.x; e < nch * MS_ROWS; e += blockDim.x) {
+    const int ci = e / MS_ROWS, i = e - ci * MS_ROWS;
+    phs[e] = i < nq ? ph[(size_t)Lc.octant[c0 + ci] * Q + q0 + i] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  f64x4 sum[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) sum[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int ci = 0; ci < nch; ++ci) {
+    const double* S = (const double*)Sc + (size_t)(c0 + ci) * Q * ncol;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+    mshift_gemm<4, double>(
+        Fs, Q, col_ok, [&](int ct, int k) { return S[(size_t)k * ncol + col[ct]]; },
+        [&](int ct, int, double v) { return valid[ct] ? v : 0.0; }, [] {}, acc);
+    // result register v of lane l is row l / 16 + 4 v of tile (t, ct)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        if (!col_ok[ct]) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const cx<double> f = phs[ci * MS_ROWS + t * 16 + (lane >> 4) + 4 * v];
+          const double mine = acc[t][ct][v], other = __shfl_xor(mine, 1);
+          sum[t][ct][v] += f.re * mine + (lane & 1 ? f.im : -f.im) * other;
+        }
+      }
+  }
+  double* out = (double*)Sp + ((size_t)p * Q + q0) * ncol;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = t * 16 + (lane >> 4) + 4 * v;
+        if (valid[ct] && i < nq) out[(size_t)i * ncol + col[ct]] = sum[t][ct][v];
+      }
 }
 
 __global__ void __launch_bounds__(256, 3) k_mshift_down(DevLevel Lc, const cx<double>* __restrict__ Gp,
@@ -858,7 +948,7 @@ __device__ __forceinline__ void translate_body(const DevLevel& Lv, const cx<TF>*
 #pragma unroll
     for (int k = 0; k < 5; ++k) acc[k] = mk<TF>(0, 0);
     if (act) {
-      const cx<TF>* Sq = S + ((size_t)r * Q + q) * 5;
+      const cx<TF>* Sq = S + ((size_t)q * R + r) * 5;
       for (int kk = gsp; kk < nil; kk += U * nsplit) {
         cx<TF> tv[U], sv[U][5];
 #pragma unroll
@@ -1438,11 +1528,20 @@ hipError_t launch_shift_up(const DevLevel& Lp, const DevLevel& Lc, const void* S
   // shorter work items) otherwise
   if (sizeof(TF) == 8 &&
       (force_mfma || Lp.nug * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS)) {
-    const int ntile = (Q + MS_ROWS - 1) / MS_ROWS, nchunk = (R + MS_RCH - 1) / MS_RCH;
+    const int ntile = (Q + MS_ROWS - 1) / MS_ROWS;
+    if (R >= TB_MIN_COLS) {
+      const int nnb = (10 * R + MS_COLS - 1) / MS_COLS;
+      const unsigned grid = 8u * (unsigned)(((Lp.nb + 7) / 8) * ntile * nnb);
+      const size_t sm = mshift_smem(Q) + 8 * MS_ROWS * sizeof(cx<double>);
+      hipLaunchKernelGGL(k_mshift_up, dim3(grid), dim3(256), sm, st, Lp, Lc, (const cx<double>*)Sc,
+                         (cx<double>*)Sp, (const double*)Ft, (const cx<double>*)ph, Q, R, ntile, nnb);
+      return hipGetLastError();
+    }
+    const int nchunk = (R + MS_RCH - 1) / MS_RCH;
     const unsigned grid = 8u * (unsigned)(((Lp.nug + 7) / 8) * ntile * nchunk);
     const size_t sm = MS_ROWS * MS_COLS * sizeof(double) + SHIFT_GROUP * MS_ROWS * sizeof(cx<double>) +
                       (SHIFT_GROUP + 1) * sizeof(int32_t);
-    hipLaunchKernelGGL(k_mshift_up, dim3(grid), dim3(256), sm, st, Lp, Lc, (const cx<double>*)Sc,
+    hipLaunchKernelGGL(k_mshift_up_groups, dim3(grid), dim3(256), sm, st, Lp, Lc, (const cx<double>*)Sc,
                        (cx<double>*)Sp, (const double*)Ft, (const cx<double>*)ph, Q, R, ntile, nchunk);
     return hipGetLastError();
   }
@@ -1475,18 +1574,19 @@ hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const
 // ---------------------------------------------------------------------------
 // Batched translation (W >= TB_MIN_COLS columns in a pass).  For one sample q
 // the translation of Eq. (4) scales whole pattern rows: the W x 5 values
-// P[box][r][q][c] of every source in a box's list are multiplied by the one
+// S[box][q][r][c] of every source in a box's list are multiplied by the one
 // factor T[off][q] and summed.  A wavefront owns (translation group, q, a
 // chunk of <= TG_COLS columns): its lanes hold the chunk's (r, c) values
-// (NS per lane), so the factor is wavefront-uniform (scalar loads) and each
-// source row loaded into registers is used for every box of the group that
-// lists it (the group's union is walked once, in ascending source order,
-// which is also each box's summation order).  Workgroup = TG_Q samples of one
-// group; chunk slowest, then the sample block, then the group: each XCD takes
-// whole sample blocks and walks the groups in Morton order, so the workgroups
-// resident on it at one time share their source rows in its L2.
+// (NS per lane; one load instruction covers 64 consecutive values of the
+// sample-major row), so the factor is wavefront-uniform (scalar loads) and
+// each source row loaded into registers is used for every box of the group
+// that lists it (the group's union is walked once, in ascending source
+// order, which is also each box's summation order).  Workgroup = TG_Q
+// samples of one group; chunk slowest, then the sample block, then the
+// group: each XCD takes whole sample blocks and walks the groups in Morton
+// order, so the workgroups resident on it at one time share their source
+// rows in its L2.  The result goes to the column-major incoming patterns.
 // ---------------------------------------------------------------------------
-constexpr int TB_MIN_COLS = 16;
 
 template <typename TF, int NS>
 __global__ void __launch_bounds__(64 * TG_Q) k_translate_rows(DevLevel Lv, const cx<TF>* __restrict__ S,
@@ -1500,12 +1600,14 @@ __global__ void __launch_bounds__(64 * TG_Q) k_translate_rows(DevLevel Lv, const
   if (q >= Q) return;
   const int lane = threadIdx.x & 63;
   const int c0 = chunk * cols, nv = 5 * min(cols, W - c0);
-  int off[NS], ld[NS];  // value offsets in a pattern row (-1: no value); load offsets (always in the row)
+  // value offsets in an incoming row (-1: no value); load offsets in an
+  // outgoing row (always in the row)
+  int off[NS], ld[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     const int e = i * 64 + lane, r = c0 + e / 5;
     off[i] = e < nv ? (r * Q + q) * 5 + e % 5 : -1;
-    ld[i] = off[i] < 0 ? 0 : off[i];
+    ld[i] = e < nv ? (q * W + c0) * 5 + e : 0;
   }
   const size_t row = (size_t)W * Q * 5;
   const int b0 = Lv.tg_box[g], nbx = Lv.tg_box[g + 1] - b0;

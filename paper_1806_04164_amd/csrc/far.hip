@@ -2,15 +2,19 @@
 // diagonal translation with the scaled plane waves of Eq. (4) and the
 // modified translation function of Eq. (5), disaggregation and reception.
 //
-// Pattern layouts of every level (W = the RHS columns of the pass, c in
-// {Jx, Jy, Jz, sigma, u}, u = div J + w^2 eps0 sigma), both box-major:
-//   outgoing S: S[((box * Q + q) * W + r) * 5 + c]   (sample-major)
-//   incoming G: G[((box * W + r) * Q + q) * 5 + c]   (column-major)
-// The translation reads every outgoing row about as many times as the
-// interaction list is long; sample-major, the W x 5 values of one (box,
-// sample) that a wavefront gathers are one contiguous run.  Its output, the
-// downward shifts and the reception take whole columns (Q x 5 contiguous).
-// With W = 1 the two layouts coincide.
+// Pattern layout (outgoing S and incoming G of every level), box-major;
+// c in {Jx, Jy, Jz, sigma, u}, u = div J + w^2 eps0 sigma, W = the RHS
+// columns of the pass:
+//   batched passes (W >= TB_MIN_COLS), sample-major:
+//     P[((box * Q + q) * W + r) * 5 + c]
+//   narrow passes, column-major:
+//     P[((box * W + r) * Q + q) * 5 + c]
+// Batched, the W x 5 values of one (box, sample) are one contiguous run: the
+// translation gathers such runs (about as many times per box as its
+// interaction list is long) and the shifts take blocks of them as GEMM
+// columns.  Narrow, a box's Q x 5 values of one column are one run, which
+// the sample lanes of the single-column kernels gather.  At W = 1 the two
+// coincide.
 #include <algorithm>
 
 #include "device.h"
@@ -20,6 +24,16 @@ namespace pie {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));  // v_mfma_f64 accumulator
 constexpr int TSET_MAX = 8;  // levels per multi-level translation launch
+constexpr int TB_MIN_COLS = 16;  // batched passes: W >= TB_MIN_COLS columns
+
+// Strides (complex elements) of the pattern value (box, q, r, c) of a pass
+// of W columns: box * Q * W * 5 + q * qs + r * rs + c.
+struct PatStride {
+  int qs, rs;
+};
+__host__ __device__ __forceinline__ PatStride pat_stride(int Q, int W) {
+  return W >= TB_MIN_COLS ? PatStride{5 * W, 5} : PatStride{5, 5 * Q};
+}
 
 // ---------------------------------------------------------------------------
 // Finest-level radiation patterns through per-incidence moments.  For a
@@ -104,6 +118,7 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
   const int b = xcd_box(blockIdx.x, nbox);
   if (b < 0) return;
   const int j0 = I.ptr[b], ni = I.ptr[b + 1] - j0;
+  const PatStride ps = pat_stride(Q, W);
   constexpr int ncol = 5 * RC;
   cx<TF>* cf = (cx<TF>*)smem;                      // [ni][6][RC]: a, -bx, -by, -bz, xp, cu
   cx<TF>* part = cf + (size_t)ni * 6 * RC;         // [nsplit - 1][Q][5][RC]
@@ -220,11 +235,11 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
 #pragma unroll
       for (int r = 0; r < RC; ++r)
         if (c0 + r < W) {
-          cx<TF>* o = S + (((size_t)b * Q + sq) * W + c0 + r) * 5;
+          cx<TF>* o = S + (size_t)b * Q * W * 5 + (size_t)sq * ps.qs + (size_t)(c0 + r) * ps.rs;
 #pragma unroll
           for (int k = 0; k < 5; ++k) o[k] = acc[k * RC + r];
           if (paired) {
-            cx<TF>* o2 = S + (((size_t)b * Q + q2) * W + c0 + r) * 5;
+            cx<TF>* o2 = S + (size_t)b * Q * W * 5 + (size_t)q2 * ps.qs + (size_t)(c0 + r) * ps.rs;
 #pragma unroll
             for (int k = 0; k < 5; ++k) o2[k] = acc2[k * RC + r];
           }
@@ -248,6 +263,7 @@ __global__ void __launch_bounds__(256) k_aggregate(DevInc I, int nbox, const cx<
 // shifts.
 // ---------------------------------------------------------------------------
 constexpr int MA_COLS = 16;  // columns per workgroup
+static_assert(MA_COLS >= TB_MIN_COLS, "the matrix-core aggregation writes sample-major patterns");
 constexpr int MA_JC = 16;    // incidences per coefficient chunk (a multiple of 4)
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_maggregate(DevInc I, int nbox, const cx<double>* __restrict__ x, int ldx,
@@ -452,6 +468,7 @@ __global__ void __launch_bounds__(256) k_shift_up(DevLevel Lp, DevLevel Lc,
   ShiftItem it;
   if (!shift_item(Lp.nug, ntile, R, SQT, it)) return;
   const int q0 = it.q0, r = it.r;
+  const PatStride ps = pat_stride(Q, R);
   const int nq = min(SQT, Q - q0);
   shift_tile(Ft, Fs, Q, q0);
   __syncthreads();
@@ -466,8 +483,8 @@ __global__ void __launch_bounds__(256) k_shift_up(DevLevel Lp, DevLevel Lc,
 #pragma unroll
   for (int i = 0; i < SQT; ++i) acc[i] = mk<TF>(0, 0);
   if (act) {
-    const cx<TF>* s = Sc + ((size_t)c * Q * R + r) * 5 + k;
-    shift_mac(Fs, qa, qb, [&](int qq) { return s[(size_t)qq * R * 5]; }, acc);
+    const cx<TF>* s = Sc + (size_t)c * Q * R * 5 + (size_t)r * ps.rs + k;
+    shift_mac(Fs, qa, qb, [&](int qq) { return s[(size_t)qq * ps.qs]; }, acc);
   }
   if (sl > 0) {
 #pragma unroll
@@ -491,7 +508,7 @@ __global__ void __launch_bounds__(256) k_shift_up(DevLevel Lp, DevLevel Lc,
     const int p = p0 + pl;
     cx<TF> v = mk<TF>(0, 0);
     for (int ch = Lp.child_ptr[p]; ch < Lp.child_ptr[p + 1]; ++ch) v = v + part[((ch - c0) * 5 + kk) * SQT + i];
-    Sp[(((size_t)p * Q + q0 + i) * R + r) * 5 + kk] = v;
+    Sp[(size_t)p * Q * R * 5 + (size_t)(q0 + i) * ps.qs + (size_t)r * ps.rs + kk] = v;
   }
 }
 
@@ -509,6 +526,7 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
   ShiftItem it;
   if (!shift_item(ng, ntile, R, SQT, it)) return;
   const int q0 = it.q0, r = it.r;
+  const PatStride ps = pat_stride(Q, R);
   const int nq = min(SQT, Q - q0);
   shift_tile(F, Fs, Q, q0);
   __syncthreads();
@@ -521,9 +539,9 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
 #pragma unroll
   for (int i = 0; i < SQT; ++i) acc[i] = mk<TF>(0, 0);
   if (act) {
-    const cx<TF>* gp = Gp + (((size_t)Lc.parent[c] * R + r) * Q) * 5 + k;
+    const cx<TF>* gp = Gp + (size_t)Lc.parent[c] * Q * R * 5 + (size_t)r * ps.rs + k;
     const cx<TF>* pc = ph + (size_t)Lc.octant[c] * Q;
-    shift_mac(Fs, qa, qb, [&](int qq) { return conj(pc[qq]) * gp[(size_t)qq * 5]; }, acc);
+    shift_mac(Fs, qa, qb, [&](int qq) { return conj(pc[qq]) * gp[(size_t)qq * ps.qs]; }, acc);
   }
   if (sl > 0) {
 #pragma unroll
@@ -534,10 +552,10 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
     for (int h = 1; h < SHIFT_SLICES; ++h)
 #pragma unroll
       for (int i = 0; i < SQT; ++i) acc[i] = acc[i] + part[((size_t)h * SHIFT_LANES + lane) * SQT + i];
-    cx<TF>* o = Gc + (((size_t)c * R + r) * Q + q0) * 5 + k;
+    cx<TF>* o = Gc + (size_t)c * Q * R * 5 + (size_t)q0 * ps.qs + (size_t)r * ps.rs + k;
 #pragma unroll
     for (int i = 0; i < SQT; ++i)
-      if (i < nq) o[(size_t)i * 5] = o[(size_t)i * 5] + acc[i];
+      if (i < nq) o[(size_t)i * ps.qs] = o[(size_t)i * ps.qs] + acc[i];
   }
 }
 
@@ -549,19 +567,16 @@ __global__ void __launch_bounds__(256) k_shift_down(DevLevel Lc, const cx<TF>* _
 // 0..31 and columns 32w .. 32w+31 (tiles past the last column are skipped).
 // The filter block is staged in LDS (zeros pad Q to whole tiles and K
 // steps) and B is read from the pattern array eight K steps at a time.
-// Upward in batched passes (sample-major outgoing patterns), the columns
-// are a block of one child's sample row and the children are phased and
-// summed in registers (narrow passes: (child, component, re/im) of a group
-// of children, as downward); downward (column-major incoming patterns), the columns are (child,
-// component, re/im) of up to SHIFT_GROUP children for one RHS column, the
-// parent's pattern is phased as it is loaded and the result is added to the
-// child's incoming pattern.
+// In batched passes the columns are a block of a sample row (W x 10 values):
+// upward, one child's rows, the children phased and summed in registers;
+// downward, the parent's rows phased for one child as they are loaded, the
+// result added to the child's incoming pattern.  Narrow passes take as
+// columns (child, component, re/im) of a group of up to SHIFT_GROUP children
+// for one RHS column.
 // Operand layout of v_mfma_f64_16x16x4 (64 lanes): lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result register v of lane l is
 // D[l / 16 + 4 v][l % 16].
 // ---------------------------------------------------------------------------
-// Batched passes: W >= TB_MIN_COLS columns take the batched kernels.
-constexpr int TB_MIN_COLS = 16;
 constexpr int MS_ROWS = 32;
 constexpr int MS_COLS = 128;
 constexpr int MS_MIN_ITEMS = 256;  // (group, row block) items for the matrix-core path
@@ -721,7 +736,7 @@ __global__ void __launch_bounds__(256, 3) k_mshift_up_groups(DevLevel Lp, DevLev
       col_ok[ct] = cbase < ncols;
       valid[ct] = col < ncols;
       const int ci = col / 10, rem = col - ci * 10;
-      base[ct] = valid[ct] ? ((size_t)(c0 + ci) * Q * R + r) * 10 + rem : 0;
+      base[ct] = valid[ct] ? (((size_t)(c0 + ci) * R + r) * Q) * 10 + rem : 0;
     }
     f64x4 acc[2][2];
 #pragma unroll
@@ -729,7 +744,7 @@ __global__ void __launch_bounds__(256, 3) k_mshift_up_groups(DevLevel Lp, DevLev
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
     mshift_gemm_ga<4, double>(
-        Ft, q0, Q, col_ok, [&](int ct, int k) { return S[base[ct] + (size_t)k * R * 10]; },
+        Ft, q0, Q, col_ok, [&](int ct, int k) { return S[base[ct] + (size_t)k * 10]; },
         [&](int ct, int, double v) { return valid[ct] ? v : 0.0; },
         [&] {
           if (r == r0) {  // phases and child ranges, once for all columns
@@ -753,7 +768,7 @@ __global__ void __launch_bounds__(256, 3) k_mshift_up_groups(DevLevel Lp, DevLev
         const double* d = Ds + i * MS_COLS + ci * 10 + 2 * kk;
         v = v + phs[ci * MS_ROWS + i] * mk(d[0], d[1]);
       }
-      Sp[(((size_t)(p0 + pl) * Q + q0 + i) * R + r) * 5 + kk] = v;
+      Sp[(((size_t)(p0 + pl) * R + r) * Q + q0 + i) * 5 + kk] = v;
     }
   }
 }
@@ -836,7 +851,11 @@ __global__ void __launch_bounds__(256, 3) k_mshift_up(DevLevel Lp, DevLevel Lc, 
       }
 }
 
-__global__ void __launch_bounds__(256, 3) k_mshift_down(DevLevel Lc, const cx<double>* __restrict__ Gp,
+// Downward shift on the matrix cores for narrow passes (W < TB_MIN_COLS):
+// columns (child, component, re/im) of SHIFT_GROUP consecutive children for
+// one RHS column at a time; the epilogue adds to the incoming patterns
+// straight from the accumulators.
+__global__ void __launch_bounds__(256, 3) k_mshift_down_groups(DevLevel Lc, const cx<double>* __restrict__ Gp,
                                                      cx<double>* __restrict__ Gc, const double* __restrict__ F,
                                                      const cx<double>* __restrict__ ph, int Q, int R, int ntile,
                                                      int nchunk) {
@@ -910,10 +929,82 @@ __global__ void __launch_bounds__(256, 3) k_mshift_down(DevLevel Lc, const cx<do
   }
 }
 
+// Downward shift on the matrix cores for batched passes (W >= TB_MIN_COLS).
+// A workgroup owns one child c and its output rows q0 .. q0 + 31 and walks
+// the MS_COLS blocks of real columns n of a sample row:
+//   G_c[q][n] += sum_k F[k][q] (conj(ph_c(k)) G_p[k])[n]
+// with the parent's sample rows phased as they are loaded (a lane loads the
+// complex value whose real or imaginary part it supplies; 16 lanes cover 128
+// consecutive bytes) and the filter block staged once for all column blocks.
+__global__ void __launch_bounds__(256, 3) k_mshift_down(DevLevel Lc, const cx<double>* __restrict__ Gp,
+                                                     cx<double>* __restrict__ Gc, const double* __restrict__ F,
+                                                     const cx<double>* __restrict__ ph, int Q, int R, int ntile) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* Fs = (double*)smem;                                              // filter block
+  cx<double>* phs = (cx<double>*)(Fs + mshift_smem(Q) / sizeof(double));   // [Q] phases of the child's octant
+  ShiftItem it;
+  if (!shift_item(Lc.nb, ntile, 1, MS_ROWS, it)) return;
+  const int c = it.g, q0 = it.q0, nq = min(MS_ROWS, Q - q0);
+  const int ncol = 10 * R, nnb = (ncol + MS_COLS - 1) / MS_COLS;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, jl = lane & 15;
+  const bool im = lane & 1;
+  const cx<double>* G = Gp + (size_t)Lc.parent[c] * Q * R * 5;
+  double* out = (double*)Gc + ((size_t)c * Q + q0) * ncol;
+  mshift_stage(F, Fs, Q, q0);
+  for (int e = threadIdx.x; e < Q; e += blockDim.x) phs[e] = ph[(size_t)Lc.octant[c] * Q + e];
+  __syncthreads();
+  for (int nb = 0; nb < nnb; ++nb) {
+    int col[2];
+    bool col_ok[2], valid[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int cbase = nb * MS_COLS + w * 32 + ct * 16;
+      col_ok[ct] = cbase < ncol;
+      valid[ct] = cbase + jl < ncol;
+      col[ct] = valid[ct] ? cbase + jl : 0;
+    }
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) acc[t][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // the child's current values (result register v of lane l is row
+    // l / 16 + 4 v of tile (t, ct)) load after the first operand batch, so
+    // that they arrive while the product runs
+    double old[2][2][4];
+    mshift_gemm<2, cx<double>>(
+        Fs, Q, col_ok, [&](int ct, int k) { return G[(size_t)k * R * 5 + (col[ct] >> 1)]; },
+        [&](int ct, int k, const cx<double>& g) {
+          const cx<double> v = conj(phs[k]) * g;
+          return valid[ct] ? (im ? v.im : v.re) : 0.0;
+        },
+        [&] {
+#pragma unroll
+          for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+              for (int v = 0; v < 4; ++v)
+                old[t][ct][v] = out[min(t * 16 + (lane >> 4) + 4 * v, nq - 1) * ncol + col[ct]];
+        },
+        acc);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = t * 16 + (lane >> 4) + 4 * v;
+          if (valid[ct] && i < nq) out[i * ncol + col[ct]] = old[t][ct][v] + acc[t][ct][v];
+        }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Translation over the interaction list at one level:
 //   G_b(q) = sum_{b' in IL(b)} T_{off(b,b')}(q) S_b'(q)
-// a gather (no atomics).  One workgroup per (box, RHS column); the list is
+// a gather (no atomics), for narrow passes (column-major patterns; batched
+// passes take k_translate_rows).  One workgroup per (box, RHS column); the list is
 // staged in LDS, thread (g, q) takes the entries g (mod nsplit) for all five
 // components with four entries' loads in flight, and the nsplit partial
 // sums are added in a fixed order through LDS.  nsplit depends on Q only,
@@ -948,7 +1039,7 @@ __device__ __forceinline__ void translate_body(const DevLevel& Lv, const cx<TF>*
 #pragma unroll
     for (int k = 0; k < 5; ++k) acc[k] = mk<TF>(0, 0);
     if (act) {
-      const cx<TF>* Sq = S + ((size_t)q * R + r) * 5;
+      const cx<TF>* Sq = S + ((size_t)r * Q + q) * 5;
       for (int kk = gsp; kk < nil; kk += U * nsplit) {
         cx<TF> tv[U], sv[U][5];
 #pragma unroll
@@ -1170,6 +1261,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 
   const int b = xcd_box(blockIdx.x, nbox);
   if (b < 0) return;
   const int j0 = I.ptr[b], ni = I.ptr[b + 1] - j0;
+  const PatStride ps = pat_stride(Q, W);
   constexpr int ncol = 5 * RC;
   const bool do_far = flags & 2, do_near = flags & 1, conj_out = flags & 4;
   cx<TF>* Gs = (cx<TF>*)smem;                              // [Q][5][RC]
@@ -1187,10 +1279,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 
     if (c0 > 0) __syncthreads();
     if (do_far) {
       for (int e = threadIdx.x; e < Q * ncol; e += blockDim.x) {
-        const int r = e / (5 * Q), qk = e - r * 5 * Q;   // source order: column, sample, component
-        const int q = qk / 5, k = qk - q * 5;
+        // source order: that of the layout (sample, column, component when
+        // batched; column, sample, component otherwise)
+        int q, r, k;
+        if (W >= TB_MIN_COLS) {
+          q = e / ncol;
+          const int rk = e - q * ncol;
+          r = rk / 5;
+          k = rk - r * 5;
+        } else {
+          r = e / (5 * Q);
+          const int qk = e - r * 5 * Q;
+          q = qk / 5;
+          k = qk - q * 5;
+        }
         Gs[(size_t)q * ncol + k * RC + r] =
-            c0 + r < W ? Gin[(((size_t)b * W + c0 + r) * Q) * 5 + qk] : mk<TF>(0, 0);
+            c0 + r < W ? Gin[(size_t)b * Q * W * 5 + (size_t)q * ps.qs + (size_t)(c0 + r) * ps.rs + k]
+                       : mk<TF>(0, 0);
       }
     }
     __syncthreads();
@@ -1292,6 +1397,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RC == 
 // permutation then run as in k_receive.
 // ---------------------------------------------------------------------------
 constexpr int MR_COLS = 16;
+static_assert(MR_COLS >= TB_MIN_COLS, "the matrix-core reception reads sample-major patterns");
 constexpr int MR_KC = 16;  // stored samples per staged chunk (four K steps)
 constexpr int MR_MAXI = 64;  // incidences per box (four row tiles)
 
@@ -1343,13 +1449,14 @@ __global__ void __launch_bounds__(256) k_mreceive(DevInc I, DevBasis B, DevNear 
     for (int sc = 0; sc < Qh; sc += MR_KC) {
       __syncthreads();  // previous chunk consumed (and pair table / slots written)
       for (int e = threadIdx.x; e < MR_KC * 5 * MR_COLS; e += blockDim.x) {
-        const int si = e / (5 * MR_COLS), rem = e - si * (5 * MR_COLS), k = rem / MR_COLS, r = rem - k * MR_COLS;
+        // source order: sample, column, component (one contiguous run per sample)
+        const int si = e / (5 * MR_COLS), rem = e - si * (5 * MR_COLS), r = rem / 5, k = rem - r * 5;
         const int sv = sc + si;
         cx<double> a = mk(0.0, 0.0), c = mk(0.0, 0.0);
         if (sv < Qh && c0 + r < W) {
-          const cx<double>* g = Gin + (((size_t)b * W + c0 + r) * Q) * 5 + k;
-          a = g[(size_t)sv * 5];
-          if (paired) c = g[(size_t)pairt[sv] * 5];
+          const cx<double>* g = Gin + ((size_t)b * Q * W + c0 + r) * 5 + k;
+          a = g[(size_t)sv * W * 5];
+          if (paired) c = g[(size_t)pairt[sv] * W * 5];
         }
         SD[((si * 5 + k) * MR_COLS + r) * 2] = a + c;
         SD[((si * 5 + k) * MR_COLS + r) * 2 + 1] = a - c;
@@ -1557,10 +1664,18 @@ hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const
                              int R, bool force_mfma, hipStream_t st) {
   const int ng = (Lc.nb + SHIFT_GROUP - 1) / SHIFT_GROUP;
   if (sizeof(TF) == 8 && (force_mfma || ng * ((Q + MS_ROWS - 1) / MS_ROWS) * (R >= 16 ? 16 : 1) >= MS_MIN_ITEMS)) {
-    const int ntile = (Q + MS_ROWS - 1) / MS_ROWS, nchunk = (R + MS_RCH - 1) / MS_RCH;
+    const int ntile = (Q + MS_ROWS - 1) / MS_ROWS;
+    if (R >= TB_MIN_COLS) {
+      const unsigned grid = 8u * (unsigned)(((Lc.nb + 7) / 8) * ntile);
+      const size_t sm = mshift_smem(Q) + (size_t)Q * sizeof(cx<double>);
+      hipLaunchKernelGGL(k_mshift_down, dim3(grid), dim3(256), sm, st, Lc, (const cx<double>*)Gp,
+                         (cx<double>*)Gc, (const double*)F, (const cx<double>*)ph, Q, R, ntile);
+      return hipGetLastError();
+    }
+    const int nchunk = (R + MS_RCH - 1) / MS_RCH;
     const unsigned grid = 8u * (unsigned)(((ng + 7) / 8) * ntile * nchunk);
     const size_t sm = mshift_smem(Q) + 8 * (size_t)Q * sizeof(cx<double>);
-    hipLaunchKernelGGL(k_mshift_down, dim3(grid), dim3(256), sm, st, Lc, (const cx<double>*)Gp, (cx<double>*)Gc,
+    hipLaunchKernelGGL(k_mshift_down_groups, dim3(grid), dim3(256), sm, st, Lc, (const cx<double>*)Gp, (cx<double>*)Gc,
                        (const double*)F, (const cx<double>*)ph, Q, R, ntile, nchunk);
     return hipGetLastError();
   }
@@ -1585,7 +1700,7 @@ hipError_t launch_shift_down(const DevLevel& Lc, const void* Gp, void* Gc, const
 // samples of one group; chunk slowest, then the sample block, then the
 // group: each XCD takes whole sample blocks and walks the groups in Morton
 // order, so the workgroups resident on it at one time share their source
-// rows in its L2.  The result goes to the column-major incoming patterns.
+// rows in its L2.
 // ---------------------------------------------------------------------------
 
 template <typename TF, int NS>
@@ -1600,14 +1715,13 @@ __global__ void __launch_bounds__(64 * TG_Q) k_translate_rows(DevLevel Lv, const
   if (q >= Q) return;
   const int lane = threadIdx.x & 63;
   const int c0 = chunk * cols, nv = 5 * min(cols, W - c0);
-  // value offsets in an incoming row (-1: no value); load offsets in an
-  // outgoing row (always in the row)
+  // value offsets in a pattern row (-1: no value); load offsets (always in the row)
   int off[NS], ld[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    const int e = i * 64 + lane, r = c0 + e / 5;
-    off[i] = e < nv ? (r * Q + q) * 5 + e % 5 : -1;
-    ld[i] = e < nv ? (q * W + c0) * 5 + e : 0;
+    const int e = i * 64 + lane;
+    off[i] = e < nv ? (q * W + c0) * 5 + e : -1;
+    ld[i] = off[i] < 0 ? 0 : off[i];
   }
   const size_t row = (size_t)W * Q * 5;
   const int b0 = Lv.tg_box[g], nbx = Lv.tg_box[g + 1] - b0;

@@ -19,6 +19,9 @@ Contents, each written from the paper (arXiv:1806.04164) and plain mathematics:
 * ``mlfma``    the MLFMA steps of Section 3 in FP64: radiation patterns,
                aggregation, translation with Eqs. (4)-(5), disaggregation.
 * ``gmres``    plain restarted GMRES (Section 4).
+* ``schwarz``  restricted additive Schwarz preconditioner over finest-box
+               near neighbourhoods (a reading: the paper names no
+               preconditioner).
 * ``mie``      Mie series for a PEC sphere (Section 4's analytic reference).
 
 Parity status of each function is stated in its docstring; anything without

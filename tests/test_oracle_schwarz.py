@@ -78,3 +78,25 @@ def test_sphere_at_very_low_frequency():
     print("unpreconditioned residual after", it0, "iterations", r0, "; preconditioned", it1, "iterations, residual", res)
     assert it0 == 250 and r0 > 1e-6
     assert it1 <= 60 and res <= 2e-6
+
+
+def test_near_mask():
+    # a mask that keeps every pair reproduces the unmasked operator exactly;
+    # a mask that keeps only pairs inside a box turns a neighbourhood's local
+    # matrix block-diagonal, so the kept rows of its inverse see only the own box
+    A, rng = _random_system(24, 3)
+    perm = rng.permutation(24)
+    boxes = [np.sort(perm[:8]), np.sort(perm[8:15]), np.sort(perm[15:])]
+    nbh = [np.concatenate([boxes[i], boxes[(i + 1) % 3]]) for i in range(3)]
+    full = schwarz.build(A, boxes, nbh)
+    keep = schwarz.build(A, boxes, nbh, near=np.ones((24, 24), bool))
+    for (_, _, m1), (_, _, m2) in zip(full, keep):
+        assert np.array_equal(m1, m2)
+    box_of = np.empty(24, int)
+    for i, b in enumerate(boxes):
+        box_of[b] = i
+    own_only = schwarz.build(A, boxes, nbh, near=box_of[:, None] == box_of[None, :])
+    v = rng.standard_normal(24) + 1j * rng.standard_normal(24)
+    y = schwarz.apply(own_only, v)
+    for b in boxes:
+        assert np.linalg.norm(A[np.ix_(b, b)] @ y[b] - v[b]) < 1e-12 * np.linalg.norm(v[b])
